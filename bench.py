@@ -1,0 +1,147 @@
+"""Benchmark: batched small-array sorting on one MI355X.
+
+Default workload (the one the throughput target is stated for): 2^24 arrays
+of n = 16 uint32 keys, uniform random, packed at stride 16, sorted in place by
+one comparator network per array.  A step is one sort call over the whole
+batch (one kernel launch).  The network is data-oblivious -- every step runs
+the same instructions and moves the same bytes whatever the data -- so the
+steps after the first re-sort the same, now sorted, buffer at identical cost.
+
+Prints one JSON line: keys/s, the roofline of the dominant kernel (algorithmic
+HBM bytes per launch / its event-timed duration vs 8 TB/s), and the CPU oracle
+timed on a bounded sample on the host cores.
+
+Other workloads (``--workload``): rss (2^20 CSR arrays of 17..256 int32 keys),
+ragged (10^7 geometric segments, uint64 keys + uint32 payload; persistent
+graph launch and the plain per-class baseline), serve (the serving loop).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--workload", default="fixed16_u32",
+                   choices=["fixed16_u32", "rss", "ragged", "serve"])
+    p.add_argument("--n", type=int, default=16)
+    p.add_argument("--count-log2", type=int, default=24)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2002_05599_amd", "csrc"))):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(ROOT, "paper_2002_05599_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch from the committed counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        data = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = data.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline_fixed(n, dtype, seconds):
+    """Oracle (insertion sort, n <= 16) on a bounded sample, all host threads."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    count = 1 << 18
+    a = np.ascontiguousarray(np.random.default_rng(9).integers(0, 2**32, size=count * n, dtype=np.uint64)
+                             .astype(dtype))
+    oracle.sort_fixed(a[: n * 1024], n, 1024, n)  # load + warm
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.sort_fixed(a, n, count, n, threads=threads)
+        done += count
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": done * n / el, "unit": "keys/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} arrays of {n} {np.dtype(dtype).name} keys (uniform), "
+                      f"{threads} host threads, {el:.1f} s"}
+
+
+def bench_fixed(args):
+    import torch
+    import paper_2002_05599_amd as ss
+    from paper_2002_05599_amd import inputs
+
+    n = args.n
+    count = 1 << args.count_log2
+    keys = torch.from_numpy(inputs.fixed_keys(np.uint32, n, count, "uniform", seed=2)).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ss.sort_small(keys, n)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ss.sort_small(keys, n)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    nkeys = count * n
+    algo_bytes = 2 * nkeys * 4
+    achieved = algo_bytes / (ms * 1e-3) / 1e9
+    kkey = f"fixed_tile_kernel<n={n},u32>"
+    tb = traffic_for(kkey)
+    out = {
+        "metric": "keys/s", "value": nkeys / (ms * 1e-3), "unit": "keys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "wall_s_timed": wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batched network sort, 2^{args.count_log2} arrays x n={n} uint32, "
+                               f"uniform, stride {n}", "n": n, "count": count, "key": "uint32"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
+                     "kernel": kkey, "algorithmic_bytes_per_launch": algo_bytes},
+    }
+    return out, (n, np.uint32)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the sorts shard into independent per-GPU batches with no communication", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "fixed16_u32":
+        out, (n, dt) = bench_fixed(args)
+        if not args.no_cpu:
+            out["cpu_baseline"] = cpu_baseline_fixed(n, dt, args.cpu_seconds)
+    else:
+        from paper_2002_05599_amd import benchmarks
+        out = benchmarks.run(args)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

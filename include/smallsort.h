@@ -1,0 +1,149 @@
+/*
+ * smallsort.h -- C ABI of libsmallsort.so: sorting very many small independent
+ * integer arrays on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Engineering Faster Sorters for Small Sets of Items" (Bingmann,
+ * Marianczuk, Sanders).  Arrays of 2..16 keys are sorted by branch-free
+ * comparator networks held in registers (Section 2); arrays of 17..256 keys by
+ * Register Sample Sort (Section 3), which splits them with sampled splitters
+ * into buckets of at most 16 keys that are finished by networks.
+ *
+ * Conventions shared by every call:
+ *   - All pointers to keys, values and offsets are DEVICE pointers (memory from
+ *     hipMalloc or any allocator returning device-accessible memory).  The
+ *     caller owns every buffer; the library never frees or retains them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued asynchronously on it; no call synchronises the host,
+ *     except ss_device_status, which says so.
+ *   - Sorting is in place and ascending (non-decreasing): the lower channel of
+ *     every comparator receives the smaller key (Section 2.1).
+ *   - Signed keys are ordered as two's-complement integers.
+ *   - With a payload (`vals` != NULL, a uint32 array parallel to the keys) the
+ *     (key, value) pairs are permuted together.  Equal keys may come out in
+ *     any order relative to each other (networks are not stable), so the
+ *     payload of equal keys is only defined as a multiset.
+ *   - Return values are ss_status codes; SS_OK is 0, errors are negative.
+ *     Argument errors are detected on the host before anything is enqueued.
+ *     Errors that depend on device data (a segment longer than 256 keys, a
+ *     decreasing offset) are recorded in a per-device status word, read with
+ *     ss_device_status; the affected segment is left unsorted.
+ *   - Working memory (counters, size-class lists, graph cache) is allocated
+ *     once per device on first use and grown when a larger batch arrives;
+ *     calls of the same or smaller shape allocate nothing.
+ *   - Calls are thread-safe; calls that overlap on one device share its
+ *     working memory, so concurrent segmented sorts must use one stream or be
+ *     externally ordered.
+ */
+#ifndef SMALLSORT_H
+#define SMALLSORT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ss_status;
+
+#define SS_OK        0
+#define SS_EINVAL   (-1)  /* bad size, count, stride or pointer */
+#define SS_EALIGN   (-2)  /* a pointer not aligned to its element size */
+#define SS_ETOOBIG  (-3)  /* an array or segment longer than SS_MAX_N */
+#define SS_EHIP     (-4)  /* a HIP runtime call failed */
+#define SS_ENOMEM   (-5)  /* working memory could not be allocated */
+#define SS_ENOTUNE  (-6)  /* unknown tuning name or unreadable tuning file */
+
+#define SS_MAX_NETWORK_N 16   /* largest array sorted by a network alone */
+#define SS_MAX_N        256   /* largest array or segment */
+
+/* Key type codes for the generic entry points. */
+#define SS_KEY_U32 0
+#define SS_KEY_I32 1
+#define SS_KEY_U64 2
+#define SS_KEY_I64 3
+
+/* Execution modes for ss_segmented_sort. */
+#define SS_MODE_AUTO       0  /* persistent kernel, replayed from a cached hipGraph */
+#define SS_MODE_PERSISTENT 1  /* persistent kernel, launched directly (no graph) */
+#define SS_MODE_PLAIN      2  /* one ordinary launch per size class */
+
+/*
+ * Fixed layout (Sections 2 and 3; the ArrayInRow arrangement of Section 4.1):
+ * array i occupies keys[i*stride, i*stride + n) for 0 <= i < count.  Entries
+ * [n, stride) of each row are neither read nor written.
+ *   n:      0..256.  n <= 1 or count == 0 is a no-op returning SS_OK.
+ *           2..16 use one comparator network per array; 17..256 use
+ *           Register Sample Sort.
+ *   stride: >= n (in keys).  count * stride keys must be addressable.
+ * Errors: SS_EINVAL for n < 0, count < 0, stride < n or keys == NULL with
+ * count > 0; SS_ETOOBIG for n > 256; SS_EALIGN if keys is not aligned to the
+ * key size; SS_EHIP if a launch fails.
+ */
+ss_status sort_small_u32(uint32_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
+ss_status sort_small_i32(int32_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
+ss_status sort_small_u64(uint64_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
+ss_status sort_small_i64(int64_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
+
+/*
+ * Segmented layout (CSR): segment i is [offsets[i], offsets[i+1]) for
+ * 0 <= i < nseg; `offsets` is a device int32 array of nseg+1 non-decreasing
+ * entries (offsets[0] need not be 0).  Segment sizes 0..256; sizes 0 and 1
+ * are no-ops.  The batch is binned by segment size (Section 5's proposal of
+ * solving base cases in batches of equal size) and sorted by one persistent
+ * launch: networks for 2..16 keys, Register Sample Sort for 17..256.
+ *   vals: NULL (keys only) or a device uint32 array indexed like keys.
+ * Errors: SS_EINVAL for nseg < 0 or a NULL pointer with nseg > 0; SS_EALIGN
+ * for misaligned pointers; SS_ENOMEM / SS_EHIP from working memory or
+ * launches.  Segments longer than 256 keys or with decreasing offsets are
+ * skipped and flagged in the device status word (SS_ETOOBIG / SS_EINVAL).
+ */
+ss_status segmented_sort_u32(uint32_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
+ss_status segmented_sort_i32(int32_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
+ss_status segmented_sort_u64(uint64_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
+ss_status segmented_sort_i64(int64_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
+
+/*
+ * Generic segmented entry point: key_type is an SS_KEY_* code, mode an
+ * SS_MODE_* code.  Same layout, ownership and errors as segmented_sort_*;
+ * SS_EINVAL for an unknown key_type or mode.  SS_MODE_PLAIN is the
+ * per-size-class baseline the persistent form is measured against.
+ */
+ss_status ss_segmented_sort(int32_t key_type, void *keys, uint32_t *vals, const int32_t *offsets,
+                            int32_t nseg, int32_t mode, void *stream);
+
+/*
+ * Reads the current device's status word after synchronising `stream`, stores
+ * it in *out (SS_OK, or the first error code recorded by a kernel) and clears
+ * it.  Returns SS_EINVAL if out is NULL, SS_EHIP if the copy fails.
+ */
+ss_status ss_device_status(void *stream, int32_t *out);
+
+/* A static, human-readable description of a status code (never NULL). */
+const char *ss_strerror(ss_status status);
+
+/*
+ * Tuning parameters (variant choices found by the autotuner).  Names:
+ *   "family"         network family for n <= 16: 0 = fewest comparators, 1 = Bose-Nelson
+ *   "rss_k_small"    splitters+1 (4, 8 or 16) for buckets of 17..64 keys
+ *   "rss_k_mid"      same for 65..128 keys
+ *   "rss_k_large"    same for 129..256 keys
+ *   "tile_chunk"     tiles claimed per atomic by the persistent kernel (1..64)
+ *   "persist_occ"    resident work-groups per CU for the persistent grid (1..16)
+ * ss_set_tuning_value returns SS_ENOTUNE for an unknown name, SS_EINVAL for a
+ * value out of range.  ss_get_tuning_value returns -1 for an unknown name.
+ * ss_load_tuning reads a flat JSON object {"name": integer, ...} with these
+ * names (other keys are ignored); SS_ENOTUNE if the file cannot be read or
+ * parsed.  Settings are process-wide and apply to later calls.
+ */
+ss_status ss_set_tuning_value(const char *name, int64_t value);
+int64_t ss_get_tuning_value(const char *name);
+ss_status ss_load_tuning(const char *json_path);
+
+/* Library version string, e.g. "smallsort 0.1 gfx950". */
+const char *ss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMALLSORT_H */

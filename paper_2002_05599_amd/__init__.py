@@ -1,1 +1,174 @@
-"""Placeholder; the binding is filled in with the C-ABI library."""
+"""Batched small-array sorting on AMD MI355X (gfx950).
+
+Thin ctypes binding over ``libsmallsort.so`` (declared in
+``include/smallsort.h``).  It only marshals arguments: every step of the sort
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+current stream.  If the library has not been built the first call raises
+``RuntimeError`` -- there is no fallback implementation.
+
+Method: Bingmann, Marianczuk, Sanders, "Engineering Faster Sorters for Small
+Sets of Items": comparator networks for 2..16 keys (Section 2) and Register
+Sample Sort for 17..256 keys (Section 3).
+"""
+import ctypes
+import os
+import threading
+
+__all__ = [
+    "SmallSortError", "lib", "lib_path", "sort_small", "segmented_sort", "device_status",
+    "set_tuning", "get_tuning", "load_tuning", "version", "KEY_CODES",
+    "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_NAME = "libsmallsort.so"
+
+MODE_AUTO, MODE_PERSISTENT, MODE_PLAIN = 0, 1, 2
+KEY_CODES = {"uint32": 0, "int32": 1, "uint64": 2, "int64": 3}
+_SUFFIX = {"uint32": "u32", "int32": "i32", "uint64": "u64", "int64": "i64"}
+
+# Every symbol include/smallsort.h declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_SIGS = {
+    **{f"sort_small_{s}": (ctypes.c_int32, [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _P])
+       for s in _SUFFIX.values()},
+    **{f"segmented_sort_{s}": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P])
+       for s in _SUFFIX.values()},
+    "ss_segmented_sort": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
+    "ss_device_status": (ctypes.c_int32, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "ss_strerror": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ss_set_tuning_value": (ctypes.c_int32, [ctypes.c_char_p, ctypes.c_int64]),
+    "ss_get_tuning_value": (ctypes.c_int64, [ctypes.c_char_p]),
+    "ss_load_tuning": (ctypes.c_int32, [ctypes.c_char_p]),
+    "ss_version": (ctypes.c_char_p, []),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class SmallSortError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        msg = lib().ss_strerror(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else f"{msg} (status {status})")
+
+
+def lib_path() -> str:
+    return os.environ.get("SMALLSORT_LIB", os.path.join(_HERE, LIB_NAME))
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            path = lib_path()
+            if not os.path.exists(path):
+                raise RuntimeError(
+                    f"{path} not found: build it with `python -m paper_2002_05599_amd.build` "
+                    "(or __graft_entry__.build()); there is no non-GPU fallback")
+            handle = ctypes.CDLL(path)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(handle, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = handle
+    return _lib
+
+
+def _check(status, what):
+    if status != 0:
+        raise SmallSortError(status, what)
+
+
+def _dtype_name(t):
+    name = str(t.dtype).replace("torch.", "")
+    if name not in _SUFFIX:
+        raise TypeError(f"unsupported key dtype {t.dtype}; use uint32, int32, uint64 or int64")
+    return name
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(t, what):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
+def sort_small(keys, n, count=None, stride=None, stream=None):
+    """Sort ``count`` arrays ``keys[i*stride : i*stride+n]`` in place (n <= 256).
+
+    ``keys`` is a contiguous device tensor of uint32/int32/uint64/int64.
+    Defaults: stride = n, count = numel // stride.
+    """
+    _require_cuda(keys, "keys")
+    name = _dtype_name(keys)
+    stride = n if stride is None else stride
+    if count is None:
+        count = keys.numel() // stride if stride > 0 else 0
+    if count * stride > keys.numel() + (stride - n if count > 0 else 0):
+        raise ValueError("keys tensor too small for count*stride")
+    f = getattr(lib(), f"sort_small_{_SUFFIX[name]}")
+    _check(f(ctypes.c_void_p(keys.data_ptr()), int(n), int(count), int(stride), _stream_ptr(stream)),
+           f"sort_small_{_SUFFIX[name]}")
+    return keys
+
+
+def segmented_sort(keys, offsets, vals=None, mode=MODE_AUTO, stream=None):
+    """Sort CSR segments ``[offsets[i], offsets[i+1])`` of ``keys`` in place.
+
+    ``offsets``: device int32 tensor of nseg+1 entries.  ``vals``: optional
+    device uint32 tensor permuted with the keys.  ``mode``: MODE_AUTO
+    (persistent kernel from a cached graph), MODE_PERSISTENT (no graph) or
+    MODE_PLAIN (one launch per size class).
+    """
+    _require_cuda(keys, "keys")
+    _require_cuda(offsets, "offsets")
+    name = _dtype_name(keys)
+    if str(offsets.dtype) != "torch.int32":
+        raise TypeError("offsets must be int32")
+    nseg = offsets.numel() - 1
+    vptr = None
+    if vals is not None:
+        _require_cuda(vals, "vals")
+        if str(vals.dtype) != "torch.uint32" or vals.numel() != keys.numel():
+            raise TypeError("vals must be a uint32 tensor shaped like keys")
+        vptr = ctypes.c_void_p(vals.data_ptr())
+    st = lib().ss_segmented_sort(KEY_CODES[name], ctypes.c_void_p(keys.data_ptr()), vptr,
+                                 ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), int(mode),
+                                 _stream_ptr(stream))
+    _check(st, "ss_segmented_sort")
+    return keys, vals
+
+
+def device_status(stream=None) -> int:
+    """Synchronise ``stream``, return and clear the device status word."""
+    out = ctypes.c_int32(0)
+    _check(lib().ss_device_status(_stream_ptr(stream), ctypes.byref(out)), "ss_device_status")
+    return out.value
+
+
+def set_tuning(name: str, value: int):
+    _check(lib().ss_set_tuning_value(name.encode(), int(value)), f"ss_set_tuning_value({name})")
+
+
+def get_tuning(name: str) -> int:
+    return int(lib().ss_get_tuning_value(name.encode()))
+
+
+def load_tuning(path: str):
+    _check(lib().ss_load_tuning(os.fsencode(path)), f"ss_load_tuning({path})")
+
+
+def version() -> str:
+    return lib().ss_version().decode()

@@ -1,0 +1,302 @@
+// C ABI of libsmallsort.so: argument checks, dispatch by size and key type,
+// tuning parameters and the per-device status word.
+#include <hip/hip_runtime.h>
+
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/smallsort.h"
+#include "internal.hpp"
+
+namespace ss {
+
+Tuning& tuning() {
+  static Tuning t;
+  return t;
+}
+
+static std::mutex g_ctx_mu;
+static std::vector<DeviceCtx*> g_ctx;
+
+DeviceCtx* device_ctx(hipError_t* err) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_ctx_mu);
+  if ((int)g_ctx.size() <= dev) g_ctx.resize(dev + 1, nullptr);
+  if (g_ctx[dev]) return g_ctx[dev];
+  DeviceCtx* c = new DeviceCtx();
+  c->device = dev;
+  e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipMalloc(&c->status, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->status, 0, sizeof(int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    if (c->status) (void)hipFree(c->status);
+    delete c;
+    *err = e;
+    return nullptr;
+  }
+  g_ctx[dev] = c;
+  return c;
+}
+
+static ss_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return SS_OK;
+  if (e == hipErrorOutOfMemory) return SS_ENOMEM;
+  return SS_EHIP;
+}
+
+template <class K>
+static ss_status check_fixed(const void* keys, int32_t n, int64_t count, int64_t stride) {
+  if (n < 0 || count < 0 || stride < 0) return SS_EINVAL;
+  if (n > SS_MAX_N) return SS_ETOOBIG;
+  if (stride < n) return SS_EINVAL;
+  if (n <= 1 || count == 0) return 1;  // no-op
+  if (keys == nullptr) return SS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(keys) % sizeof(K) != 0) return SS_EALIGN;
+  if (count > (INT64_MAX / (stride > 0 ? stride : 1))) return SS_EINVAL;
+  return SS_OK;
+}
+
+template <class K>
+static ss_status sort_small(K* keys, int32_t n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+  ss_status st = check_fixed<K>(keys, n, count, stride);
+  if (st == 1) return SS_OK;
+  if (st != SS_OK) return st;
+  hipError_t herr = hipSuccess;
+  if (n <= SS_MAX_NETWORK_N) {
+    if constexpr (sizeof(K) == 4)
+      herr = launch_fixed_u32(reinterpret_cast<uint32_t*>(keys), n, count, stride, (uint32_t)flip, s);
+    else
+      herr = launch_fixed_u64(reinterpret_cast<uint64_t*>(keys), n, count, stride, (uint64_t)flip, s);
+    return from_hip(herr);
+  }
+  DeviceCtx* c = device_ctx(&herr);
+  if (!c) return from_hip(herr);
+  if constexpr (sizeof(K) == 4)
+    herr = launch_rss_fixed_u32(reinterpret_cast<uint32_t*>(keys), n, count, stride, (uint32_t)flip,
+                                c->status, s);
+  else
+    herr = launch_rss_fixed_u64(reinterpret_cast<uint64_t*>(keys), n, count, stride, (uint64_t)flip,
+                                c->status, s);
+  return from_hip(herr);
+}
+
+static ss_status segmented(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
+                           int32_t nseg, int32_t mode, hipStream_t s) {
+  if (key_type < SS_KEY_U32 || key_type > SS_KEY_I64) return SS_EINVAL;
+  if (mode < SS_MODE_AUTO || mode > SS_MODE_PLAIN) return SS_EINVAL;
+  if (nseg < 0) return SS_EINVAL;
+  if (nseg == 0) return SS_OK;
+  if (keys == nullptr || offsets == nullptr) return SS_EINVAL;
+  const size_t ksz = (key_type == SS_KEY_U32 || key_type == SS_KEY_I32) ? 4 : 8;
+  if (reinterpret_cast<uintptr_t>(keys) % ksz != 0) return SS_EALIGN;
+  if (reinterpret_cast<uintptr_t>(offsets) % 4 != 0) return SS_EALIGN;
+  if (vals && reinterpret_cast<uintptr_t>(vals) % 4 != 0) return SS_EALIGN;
+  hipError_t herr = hipSuccess;
+  DeviceCtx* c = device_ctx(&herr);
+  if (!c) return from_hip(herr);
+  switch (key_type) {
+    case SS_KEY_U32:
+      return segmented_u32(c, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0u, mode, s);
+    case SS_KEY_I32:
+      return segmented_u32(c, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0x80000000u, mode, s);
+    case SS_KEY_U64:
+      return segmented_u64(c, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0ull, mode, s);
+    default:
+      return segmented_u64(c, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0x8000000000000000ull,
+                           mode, s);
+  }
+}
+
+// --- tuning ----------------------------------------------------------------
+
+struct TuneEntry {
+  const char* name;
+  int* slot;
+  int lo, hi;
+  bool pow2_k;  // must be 4, 8 or 16
+};
+
+static std::vector<TuneEntry> tune_table() {
+  Tuning& t = tuning();
+  return {
+      {"family", &t.family, 0, 1, false},
+      {"rss_k_small", &t.rss_k[0], 4, 16, true},
+      {"rss_k_mid", &t.rss_k[1], 4, 16, true},
+      {"rss_k_large", &t.rss_k[2], 4, 16, true},
+      {"tile_chunk", &t.tile_chunk, 1, 64, false},
+      {"persist_occ", &t.persist_occ, 0, 16, false},
+      {"rss_rounds", &t.rss_rounds, 1, 16, false},
+  };
+}
+
+static std::mutex g_tune_mu;
+
+static ss_status set_tuning(const char* name, int64_t value) {
+  if (!name) return SS_ENOTUNE;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const TuneEntry& e : tune_table()) {
+    if (std::strcmp(e.name, name) != 0) continue;
+    if (value < e.lo || value > e.hi) return SS_EINVAL;
+    if (e.pow2_k && value != 4 && value != 8 && value != 16) return SS_EINVAL;
+    *e.slot = (int)value;
+    return SS_OK;
+  }
+  return SS_ENOTUNE;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+ss_status sort_small_u32(uint32_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
+  return sort_small<uint32_t>(keys, n, count, stride, 0u, static_cast<hipStream_t>(stream));
+}
+ss_status sort_small_i32(int32_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
+  return sort_small<uint32_t>(reinterpret_cast<uint32_t*>(keys), n, count, stride, 0x80000000u,
+                              static_cast<hipStream_t>(stream));
+}
+ss_status sort_small_u64(uint64_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
+  return sort_small<uint64_t>(keys, n, count, stride, 0ull, static_cast<hipStream_t>(stream));
+}
+ss_status sort_small_i64(int64_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
+  return sort_small<uint64_t>(reinterpret_cast<uint64_t*>(keys), n, count, stride,
+                              0x8000000000000000ull, static_cast<hipStream_t>(stream));
+}
+
+ss_status segmented_sort_u32(uint32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                             void* stream) {
+  return segmented(SS_KEY_U32, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+}
+ss_status segmented_sort_i32(int32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                             void* stream) {
+  return segmented(SS_KEY_I32, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+}
+ss_status segmented_sort_u64(uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                             void* stream) {
+  return segmented(SS_KEY_U64, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+}
+ss_status segmented_sort_i64(int64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                             void* stream) {
+  return segmented(SS_KEY_I64, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+}
+
+ss_status ss_segmented_sort(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
+                            int32_t nseg, int32_t mode, void* stream) {
+  return segmented(key_type, keys, vals, offsets, nseg, mode, static_cast<hipStream_t>(stream));
+}
+
+ss_status ss_device_status(void* stream, int32_t* out) {
+  if (!out) return SS_EINVAL;
+  hipError_t herr = hipSuccess;
+  DeviceCtx* c = device_ctx(&herr);
+  if (!c) return from_hip(herr);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int value = 0;
+  herr = hipStreamSynchronize(s);
+  if (herr == hipSuccess) herr = hipMemcpy(&value, c->status, sizeof(int), hipMemcpyDeviceToHost);
+  if (herr == hipSuccess) herr = hipMemset(c->status, 0, sizeof(int));
+  if (herr == hipSuccess) herr = hipDeviceSynchronize();
+  if (herr != hipSuccess) return SS_EHIP;
+  *out = value;
+  return SS_OK;
+}
+
+const char* ss_strerror(ss_status status) {
+  switch (status) {
+    case SS_OK: return "success";
+    case SS_EINVAL: return "invalid argument (size, count, stride, pointer or offsets)";
+    case SS_EALIGN: return "pointer not aligned to its element size";
+    case SS_ETOOBIG: return "array or segment longer than 256 keys";
+    case SS_EHIP: return "HIP runtime error";
+    case SS_ENOMEM: return "out of device memory";
+    case SS_ENOTUNE: return "unknown tuning parameter or unreadable tuning file";
+    default: return "unknown status";
+  }
+}
+
+ss_status ss_set_tuning_value(const char* name, int64_t value) { return set_tuning(name, value); }
+
+int64_t ss_get_tuning_value(const char* name) {
+  if (!name) return -1;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const TuneEntry& e : tune_table())
+    if (std::strcmp(e.name, name) == 0) return *e.slot;
+  return -1;
+}
+
+// Minimal reader for a flat JSON object of integer values: {"a": 1, "b": 2}.
+ss_status ss_load_tuning(const char* json_path) {
+  if (!json_path) return SS_ENOTUNE;
+  FILE* f = std::fopen(json_path, "rb");
+  if (!f) return SS_ENOTUNE;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  size_t i = 0;
+  auto skip = [&] {
+    while (i < text.size() && std::isspace((unsigned char)text[i])) ++i;
+  };
+  skip();
+  if (i >= text.size() || text[i] != '{') return SS_ENOTUNE;
+  ++i;
+  std::vector<std::pair<std::string, int64_t>> items;
+  while (true) {
+    skip();
+    if (i < text.size() && text[i] == '}') break;
+    if (i >= text.size() || text[i] != '"') return SS_ENOTUNE;
+    size_t end = text.find('"', i + 1);
+    if (end == std::string::npos) return SS_ENOTUNE;
+    std::string key = text.substr(i + 1, end - i - 1);
+    i = end + 1;
+    skip();
+    if (i >= text.size() || text[i] != ':') return SS_ENOTUNE;
+    ++i;
+    skip();
+    // value: an integer, or any other JSON scalar/string which is skipped
+    size_t vstart = i;
+    if (i < text.size() && text[i] == '"') {
+      size_t vend = text.find('"', i + 1);
+      if (vend == std::string::npos) return SS_ENOTUNE;
+      i = vend + 1;
+    } else {
+      while (i < text.size() && text[i] != ',' && text[i] != '}') ++i;
+      std::string v = text.substr(vstart, i - vstart);
+      while (!v.empty() && std::isspace((unsigned char)v.back())) v.pop_back();
+      char* endp = nullptr;
+      long long x = std::strtoll(v.c_str(), &endp, 10);
+      if (!v.empty() && endp && *endp == '\0') items.emplace_back(key, (int64_t)x);
+    }
+    skip();
+    if (i < text.size() && text[i] == ',') {
+      ++i;
+      continue;
+    }
+    skip();
+    if (i < text.size() && text[i] == '}') break;
+    return SS_ENOTUNE;
+  }
+  for (auto& kv : items) {
+    ss_status st = set_tuning(kv.first.c_str(), kv.second);
+    if (st == SS_EINVAL) return SS_EINVAL;
+  }
+  return SS_OK;
+}
+
+const char* ss_version(void) { return "smallsort 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// Comparator-network sort of many arrays of N = 2..16 keys (paper, Section 2).
+//
+// One thread sorts one array held in N registers (Section 2.2: straight-line
+// conditional swaps with no branches; here each swap is v_min/v_max for 32-bit
+// keys).  Arrays sit back to back in HBM (the ArrayInRow layout of
+// Section 4.1), so a thread's own keys are N*sizeof(K) contiguous bytes and a
+// direct per-thread load would touch a different 16-byte piece of many cache
+// lines per instruction.  Instead a 256-thread work-group stages its tile of
+// 256 arrays through LDS:
+//
+//   HBM --(16-byte coalesced loads, consecutive lanes -> consecutive bytes)--> VGPRs
+//       --(LDS write in a conflict-avoiding layout)--> LDS
+//       --(each thread reads its own row)--> N VGPRs --network--> LDS --> HBM
+//
+// LDS layouts (chosen at compile time from N and the key size E):
+//   * vector layout, when N*E is a multiple of 16: each array is C = N*E/16
+//     chunks of 16 bytes; chunk k of array a is stored in slot a*C + rot(a, k)
+//     with a per-array rotation, so the 16-byte reads of 8 neighbouring
+//     threads (one LDS pass) fall in distinct bank groups;
+//   * element layout otherwise: array a occupies elements [a*P, a*P+N) with
+//     an odd pitch P (N or N+1), so a wave's per-thread element reads hit
+//     distinct banks.
+// The last, partial tile (count not a multiple of 256) takes element-wise
+// global accesses guarded by bounds.  A stride other than N, or a base pointer
+// that is not 16-byte aligned, uses the direct per-thread kernel instead.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ss {
+
+constexpr int kTileThreads = 256;
+
+// Native 16-byte vector (the HIP uint4 struct is not accepted by the
+// non-temporal builtins).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int N, class K> struct TileLayout {
+  static constexpr int E = (int)sizeof(K);
+  static constexpr bool kVec = (N * E) % 16 == 0;
+  static constexpr int C = kVec ? N * E / 16 : 1;   // 16-byte chunks per array
+  static constexpr int P = (N % 2) ? N : N + 1;    // element pitch (element layout)
+  static constexpr int kBytes = kVec ? kTileThreads * N * E : kTileThreads * P * E;
+  static constexpr int kPerChunk = 16 / E;         // keys per 16-byte chunk
+  // Rotation step: threads a and a' whose rows start in the same bank group
+  // within one 8-thread pass get different rotations.
+  static constexpr int kRotShift = (C == 2) ? 2 : (C == 4) ? 1 : (C == 6) ? 2 : 0;
+
+  __device__ __forceinline__ static int chunk_slot(int a, int k) {
+    if constexpr (C % 2 == 1) {
+      return a * C + k;
+    } else {
+      int r = (a >> kRotShift) % C;
+      int kk = k + r;
+      kk = kk >= C ? kk - C : kk;
+      return a * C + kk;
+    }
+  }
+  // Byte offset in LDS of key j of array a.
+  __device__ __forceinline__ static int elem_offset(int a, int j) {
+    if constexpr (kVec) {
+      return chunk_slot(a, j / kPerChunk) * 16 + (j % kPerChunk) * E;
+    } else {
+      return (a * P + j) * E;
+    }
+  }
+};
+
+template <class K> __device__ __forceinline__ K lds_ld(const unsigned char* p) {
+  return *reinterpret_cast<const K*>(p);
+}
+template <class K> __device__ __forceinline__ void lds_st(unsigned char* p, K v) {
+  *reinterpret_cast<K*>(p) = v;
+}
+
+template <int F, int N, class K>
+__global__ void __launch_bounds__(kTileThreads)
+fixed_tile_kernel(K* __restrict__ keys, int64_t count, K flip) {
+  using L = TileLayout<N, K>;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
+  constexpr int kChunks = kTileThreads * N * L::E / 16;  // 16-byte chunks in a full tile
+  constexpr int kIters = (kChunks + kTileThreads - 1) / kTileThreads;
+  constexpr bool kExact = (kChunks % kTileThreads) == 0;
+
+  const int t = threadIdx.x;
+  const int64_t first = (int64_t)blockIdx.x * kTileThreads;
+  const int64_t left = count - first;
+  const int valid = left < kTileThreads ? (int)left : kTileThreads;
+  K* gk = keys + first * N;
+  const bool full = valid == kTileThreads;
+
+  if (full) {
+    const u32x4* g4 = reinterpret_cast<const u32x4*>(gk);
+    u32x4 buf[kIters];
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+      int g = t + i * kTileThreads;
+      if (kExact || g < kChunks) buf[i] = __builtin_nontemporal_load(g4 + g);
+    }
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+      int g = t + i * kTileThreads;
+      if (kExact || g < kChunks) {
+        if constexpr (L::kVec) {
+          int a = g / L::C, k = g - (g / L::C) * L::C;
+          *reinterpret_cast<u32x4*>(lds + L::chunk_slot(a, k) * 16) = buf[i];
+        } else {
+          K parts[L::kPerChunk];
+          __builtin_memcpy(parts, &buf[i], 16);
+#pragma unroll
+          for (int q = 0; q < L::kPerChunk; ++q) {
+            int e = g * L::kPerChunk + q;
+            int a = e / N, j = e - (e / N) * N;
+            lds_st<K>(lds + L::elem_offset(a, j), parts[q]);
+          }
+        }
+      }
+    }
+  } else {
+    const int nelem = valid * N;
+    for (int e = t; e < nelem; e += kTileThreads) {
+      int a = e / N, j = e - (e / N) * N;
+      lds_st<K>(lds + L::elem_offset(a, j), gk[e]);
+    }
+  }
+  __syncthreads();
+
+  if (t < valid) {
+    K r[N];
+    if constexpr (L::kVec) {
+#pragma unroll
+      for (int k = 0; k < L::C; ++k) {
+        u32x4 q = *reinterpret_cast<const u32x4*>(lds + L::chunk_slot(t, k) * 16);
+        __builtin_memcpy(&r[k * L::kPerChunk], &q, 16);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = lds_ld<K>(lds + L::elem_offset(t, j));
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] ^= flip;
+    net_sort<F, N>(r);
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] ^= flip;
+    if constexpr (L::kVec) {
+#pragma unroll
+      for (int k = 0; k < L::C; ++k) {
+        u32x4 q;
+        __builtin_memcpy(&q, &r[k * L::kPerChunk], 16);
+        *reinterpret_cast<u32x4*>(lds + L::chunk_slot(t, k) * 16) = q;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) lds_st<K>(lds + L::elem_offset(t, j), r[j]);
+    }
+  }
+  __syncthreads();
+
+  if (full) {
+    u32x4* g4 = reinterpret_cast<u32x4*>(gk);
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+      int g = t + i * kTileThreads;
+      if (kExact || g < kChunks) {
+        u32x4 v;
+        if constexpr (L::kVec) {
+          int a = g / L::C, k = g - (g / L::C) * L::C;
+          v = *reinterpret_cast<const u32x4*>(lds + L::chunk_slot(a, k) * 16);
+        } else {
+          K parts[L::kPerChunk];
+#pragma unroll
+          for (int q = 0; q < L::kPerChunk; ++q) {
+            int e = g * L::kPerChunk + q;
+            int a = e / N, j = e - (e / N) * N;
+            parts[q] = lds_ld<K>(lds + L::elem_offset(a, j));
+          }
+          __builtin_memcpy(&v, parts, 16);
+        }
+        __builtin_nontemporal_store(v, g4 + g);
+      }
+    }
+  } else {
+    const int nelem = valid * N;
+    for (int e = t; e < nelem; e += kTileThreads) {
+      int a = e / N, j = e - (e / N) * N;
+      gk[e] = lds_ld<K>(lds + L::elem_offset(a, j));
+    }
+  }
+}
+
+// One thread per array, direct global accesses: any stride, any alignment.
+template <int F, int N, class K>
+__global__ void __launch_bounds__(kTileThreads)
+fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, K flip) {
+  const int64_t a = (int64_t)blockIdx.x * kTileThreads + threadIdx.x;
+  if (a >= count) return;
+  K* p = keys + a * stride;
+  K r[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) r[j] = p[j] ^ flip;
+  net_sort<F, N>(r);
+#pragma unroll
+  for (int j = 0; j < N; ++j) p[j] = r[j] ^ flip;
+}
+
+template <int F, int N, class K>
+static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, K flip, hipStream_t s) {
+  const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
+  if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
+  if (tiled) {
+    hipLaunchKernelGGL((fixed_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s,
+                       keys, count, flip);
+  } else {
+    hipLaunchKernelGGL((fixed_direct_kernel<F, N, K>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s,
+                       keys, count, stride, flip);
+  }
+  return hipGetLastError();
+}
+
+template <int F, class K>
+static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+  switch (n) {
+    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, s);
+    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, s);
+    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, s);
+    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, s);
+    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, s);
+    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, s);
+    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, s);
+    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, s);
+    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, s);
+    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, s);
+    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, s);
+    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, s);
+    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, s);
+    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, s);
+    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+                            hipStream_t s) {
+  return tuning().family == 1 ? launch_fixed_f<1>(keys, n, count, stride, flip, s)
+                              : launch_fixed_f<0>(keys, n, count, stride, flip, s);
+}
+hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+                            hipStream_t s) {
+  return tuning().family == 1 ? launch_fixed_f<1>(keys, n, count, stride, flip, s)
+                              : launch_fixed_f<0>(keys, n, count, stride, flip, s);
+}
+
+}  // namespace ss

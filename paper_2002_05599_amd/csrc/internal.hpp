@@ -1,0 +1,52 @@
+// Host-side interfaces between the C ABI (capi.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ss {
+
+// Variant choices, set by the autotuner through ss_set_tuning_value.
+struct Tuning {
+  int family = 0;        // network family for n <= 16 (0 fewest comparators, 1 Bose-Nelson)
+  int rss_k[3] = {4, 8, 16};  // level-0 bucket count for 17..64, 65..128, 129..256 keys
+  int tile_chunk = 1;    // tiles claimed per atomic in the persistent kernel
+  int persist_occ = 0;   // work-groups per CU for the persistent grid (0 = occupancy limit)
+  int rss_rounds = 4;    // rounds of groups per RSS tile in the segmented kernels
+};
+Tuning& tuning();
+
+// Fixed layout, n = 2..16 (networks).  flip = sign-bit mask (0 for unsigned).
+hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+                            hipStream_t s);
+hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+                            hipStream_t s);
+
+// Fixed layout, n = 17..256 (Register Sample Sort).
+hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+                                int* status, hipStream_t s);
+hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+                                int* status, hipStream_t s);
+
+// Per-device context: status word, device properties and working memory
+// for the segmented path (grown on demand, freed at process exit).
+struct SegmentedCache;  // defined with the segmented kernels
+struct DeviceCtx {
+  int device = -1;
+  int num_cus = 0;
+  int* status = nullptr;          // device int32 status word
+  SegmentedCache* seg = nullptr;  // working memory + graphs of the segmented path
+};
+// Context of the current device, created on first use; nullptr on failure
+// with *err set to a HIP error.
+DeviceCtx* device_ctx(hipError_t* err);
+
+// Segmented (CSR) sorting; returns an ss_status code.
+// mode: 0 persistent kernel from a cached graph, 1 persistent kernel launched
+// directly, 2 one plain launch per size class.
+int segmented_u32(DeviceCtx* c, uint32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                  uint32_t flip, int mode, hipStream_t s);
+int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                  uint64_t flip, int mode, hipStream_t s);
+
+}  // namespace ss

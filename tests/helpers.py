@@ -1,0 +1,44 @@
+"""Shared test helpers: device transfer and comparisons against the oracle."""
+import numpy as np
+
+_TORCH_DT = None
+
+
+def torch_dtype(np_dtype):
+    import torch
+    return {np.dtype(np.uint32): torch.uint32, np.dtype(np.int32): torch.int32,
+            np.dtype(np.uint64): torch.uint64, np.dtype(np.int64): torch.int64}[np.dtype(np_dtype)]
+
+
+def to_dev(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def from_dev(t) -> np.ndarray:
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def first_mismatch(got: np.ndarray, want: np.ndarray, row: int = 0):
+    """Human-readable description of the first differing row (row length ``row``)."""
+    bad = np.nonzero(got != want)[0]
+    if bad.size == 0:
+        return None
+    i = int(bad[0])
+    if row:
+        r = i // row
+        return f"row {r}: got {got[r*row:(r+1)*row]} want {want[r*row:(r+1)*row]}"
+    return f"index {i}: got {got[i]} want {want[i]}"
+
+
+def pairs_multiset_equal(k1, v1, k2, v2, offsets):
+    """Per segment, the multisets of (key, val) pairs agree."""
+    for i in range(offsets.size - 1):
+        lo, hi = offsets[i], offsets[i + 1]
+        a = sorted(zip(k1[lo:hi].tolist(), v1[lo:hi].tolist()))
+        b = sorted(zip(k2[lo:hi].tolist(), v2[lo:hi].tolist()))
+        if a != b:
+            return i
+    return None

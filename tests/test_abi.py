@@ -1,0 +1,88 @@
+"""The C-ABI library loads and exports what include/smallsort.h declares (no GPU compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2002_05599_amd as ss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smallsort.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_0-9]+)\s*\([^;{]*\)\s*;", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ss.lib_path()):
+        pytest.fail("libsmallsort.so is not built (run __graft_entry__.build())")
+    return ss.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ["sort_small_u32", "sort_small_i32", "sort_small_u64", "sort_small_i64",
+                 "segmented_sort_u32", "segmented_sort_i32", "segmented_sort_u64", "segmented_sort_i64",
+                 "ss_segmented_sort", "ss_device_status", "ss_strerror", "ss_load_tuning",
+                 "ss_set_tuning_value", "ss_get_tuning_value", "ss_version"]:
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = ctypes.CDLL(ss.lib_path())
+    for name in declared_functions():
+        assert hasattr(raw, name), f"{name} declared but not exported"
+    assert set(declared_functions()) <= set(ss._SIGS), "binding misses a declared function"
+
+
+def test_strerror_and_version(lib):
+    assert lib.ss_strerror(0) == b"success"
+    assert b"aligned" in lib.ss_strerror(-2)
+    assert lib.ss_strerror(12345) == b"unknown status"
+    assert ss.version().startswith("smallsort")
+
+
+def test_argument_errors_need_no_device(lib):
+    p = ctypes.c_void_p(0x1000)
+    # n > 256, stride < n, negative sizes, misalignment: rejected on the host
+    assert lib.sort_small_u32(p, 257, 1, 257, None) == -3
+    assert lib.sort_small_u32(p, 8, 1, 7, None) == -1
+    assert lib.sort_small_u32(p, -1, 1, 8, None) == -1
+    assert lib.sort_small_u32(p, 8, -5, 8, None) == -1
+    assert lib.sort_small_u64(ctypes.c_void_p(0x1004), 8, 1, 8, None) == -2
+    assert lib.sort_small_u32(None, 8, 3, 8, None) == -1
+    # no-ops succeed without touching memory
+    assert lib.sort_small_u32(None, 8, 0, 8, None) == 0
+    assert lib.sort_small_i64(None, 1, 100, 1, None) == 0
+    assert lib.sort_small_i32(p, 0, 100, 0, None) == 0
+    assert lib.ss_segmented_sort(0, None, None, None, 0, 0, None) == 0
+    assert lib.ss_segmented_sort(0, None, None, None, -1, 0, None) == -1
+    assert lib.ss_segmented_sort(7, p, None, p, 1, 0, None) == -1
+    assert lib.ss_segmented_sort(0, p, None, p, 1, 9, None) == -1
+    assert lib.ss_segmented_sort(2, ctypes.c_void_p(0x1004), None, p, 1, 0, None) == -2
+    assert lib.ss_device_status(None, None) == -1
+
+
+def test_tuning_roundtrip(lib, tmp_path):
+    old = ss.get_tuning("rss_k_small")
+    ss.set_tuning("rss_k_small", 8)
+    assert ss.get_tuning("rss_k_small") == 8
+    with pytest.raises(ss.SmallSortError):
+        ss.set_tuning("rss_k_small", 5)
+    with pytest.raises(ss.SmallSortError):
+        ss.set_tuning("no_such_knob", 1)
+    assert ss.get_tuning("no_such_knob") == -1
+    f = tmp_path / "t.json"
+    f.write_text('{"rss_k_small": 16, "family": 1, "note": "x", "other": 3.5}')
+    ss.load_tuning(str(f))
+    assert ss.get_tuning("rss_k_small") == 16 and ss.get_tuning("family") == 1
+    f.write_text('{"rss_k_small": 4, ')
+    with pytest.raises(ss.SmallSortError):
+        ss.load_tuning(str(f))
+    ss.set_tuning("family", 0)
+    ss.set_tuning("rss_k_small", old)
