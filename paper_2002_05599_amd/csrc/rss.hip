@@ -1,0 +1,60 @@
+// Register Sample Sort of many arrays of 17..256 keys in the fixed layout
+// (array i at keys[i*stride, i*stride+n)).  A 256-thread work-group holds four
+// waves; each wave sorts 64/G arrays at once, one per G-lane group, with
+// G = 16 for n <= 64, 32 for n <= 128 and 64 above (at most 4 keys per lane).
+#include "internal.hpp"
+#include "rss.hpp"
+
+namespace ss {
+
+constexpr int kRssThreads = 256;
+constexpr int kRssWaves = kRssThreads / kWave;
+
+template <int F, class K, int G>
+__global__ void __launch_bounds__(kRssThreads)
+rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip, int k0) {
+  constexpr int kGroups = kWave / G;
+  __shared__ GroupLds<K, false, G> lds[kRssWaves * kGroups];
+  const int wave = threadIdx.x / kWave;
+  const int g = lane_id() / G;
+  const int64_t arr = ((int64_t)blockIdx.x * kRssWaves + wave) * kGroups + g;
+  const int m = arr < count ? n : 0;
+  K* gk = keys + (arr < count ? arr * stride : 0);
+  rss_group_sort<F, K, false, G>(lds[wave * kGroups + g], gk, nullptr, m, flip, k0);
+}
+
+template <int F, class K, int G>
+static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, K flip, int k0,
+                               hipStream_t s) {
+  constexpr int per_block = kRssWaves * (kWave / G);
+  const int64_t blocks = (count + per_block - 1) / per_block;
+  if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((rss_fixed_kernel<F, K, G>), dim3((unsigned)blocks), dim3(kRssThreads), 0, s, keys, n,
+                     count, stride, flip, k0);
+  return hipGetLastError();
+}
+
+template <int F, class K>
+static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+  const Tuning& t = tuning();
+  if (n <= 64) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], s);
+  if (n <= 128) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], s);
+  return launch_rss_g<F, K, 64>(keys, n, count, stride, flip, t.rss_k[2], s);
+}
+
+hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+                                int* status, hipStream_t s) {
+  (void)status;
+  if (n < 17 || n > kMaxN) return hipErrorInvalidValue;
+  return tuning().family == 1 ? launch_rss_f<1>(keys, n, count, stride, flip, s)
+                              : launch_rss_f<0>(keys, n, count, stride, flip, s);
+}
+hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+                                int* status, hipStream_t s) {
+  (void)status;
+  if (n < 17 || n > kMaxN) return hipErrorInvalidValue;
+  return tuning().family == 1 ? launch_rss_f<1>(keys, n, count, stride, flip, s)
+                              : launch_rss_f<0>(keys, n, count, stride, flip, s);
+}
+
+}  // namespace ss

@@ -1,0 +1,107 @@
+"""Parity of Register Sample Sort (n = 17..256, fixed layout) with the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2002_05599_amd as ss
+from paper_2002_05599_amd import inputs
+from helpers import first_mismatch, from_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TYPES = [np.uint32, np.int32, np.uint64, np.int64]
+SIZES = [17, 18, 24, 31, 32, 33, 47, 63, 64, 65, 96, 127, 128, 129, 160, 200, 255, 256]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    ss.lib()
+    yield
+    assert ss.device_status() == 0
+
+
+def run_fixed(a, n, count, stride):
+    t = to_dev(a)
+    ss.sort_small(t, n, count=count, stride=stride)
+    return from_dev(t)
+
+
+def special(dtype, n, count, kind, seed):
+    info = np.iinfo(dtype)
+    rng = np.random.default_rng(seed)
+    if kind == "all_equal":
+        return np.full(n * count, 12345, dtype=dtype)
+    if kind == "two_values":
+        return np.where(rng.random(n * count) < 0.5, 7, 9).astype(dtype)
+    if kind == "max_heavy":
+        a = inputs.random_keys(dtype, n * count, seed)
+        a[rng.random(n * count) < 0.4] = info.max
+        a[rng.random(n * count) < 0.1] = info.min
+        return a
+    if kind == "zipf":
+        return inputs.zipf_keys(n * count, seed).astype(dtype)
+    if kind == "organ":
+        row = np.concatenate([np.arange(n // 2), np.arange(n - n // 2)[::-1]]).astype(dtype)
+        return np.tile(row, count)
+    if kind == "one_big_dup":
+        a = inputs.random_keys(dtype, n * count, seed)
+        a[rng.random(n * count) < 0.8] = 42
+        return a
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("dtype", TYPES, ids=lambda d: np.dtype(d).name)
+@pytest.mark.parametrize("n", SIZES)
+def test_rss_distributions(n, dtype):
+    count = 4 * 16 + 5  # several work-groups and a ragged tail at every group size
+    for k, dist in enumerate(inputs.DISTRIBUTIONS):
+        a = inputs.fixed_keys(dtype, n, count, dist, seed=1000 + 13 * n + k)
+        got = run_fixed(a, n, count, n)
+        want = oracle.sort_fixed(a, n, count, n)
+        assert (got == want).all(), f"{dist}: {first_mismatch(got, want, n)}"
+
+
+@pytest.mark.parametrize("kind", ["all_equal", "two_values", "max_heavy", "zipf", "organ", "one_big_dup"])
+@pytest.mark.parametrize("dtype", [np.uint32, np.int64], ids=lambda d: np.dtype(d).name)
+def test_rss_duplicates_and_extremes(kind, dtype):
+    for n in (17, 40, 64, 100, 128, 256):
+        count = 37
+        a = special(dtype, n, count, kind, seed=n)
+        got = run_fixed(a, n, count, n)
+        want = oracle.sort_fixed(a, n, count, n)
+        assert (got == want).all(), f"{kind} n={n}: {first_mismatch(got, want, n)}"
+
+
+def test_rss_every_size_u32():
+    """Every n in 17..256 once (u32, uniform)."""
+    for n in range(17, 257):
+        count = 9
+        a = inputs.random_keys(np.uint32, n * count, seed=n * 7)
+        got = run_fixed(a, n, count, n)
+        want = oracle.sort_fixed(a, n, count, n)
+        assert (got == want).all(), f"n={n}: {first_mismatch(got, want, n)}"
+
+
+@pytest.mark.parametrize("tuning", [("rss_k_small", 16), ("rss_k_mid", 4), ("rss_k_large", 4),
+                                    ("rss_k_large", 8), ("family", 1)])
+def test_rss_tuning_variants(tuning):
+    name, value = tuning
+    old = ss.get_tuning(name)
+    ss.set_tuning(name, value)
+    try:
+        for n in (20, 64, 100, 256):
+            a = inputs.random_keys(np.int32, n * 50, seed=n)
+            got = run_fixed(a, n, 50, n)
+            assert (got == oracle.sort_fixed(a, n, 50, n)).all(), (name, value, n)
+    finally:
+        ss.set_tuning(name, old)
+
+
+def test_rss_stride_and_repeat():
+    n, stride, count = 100, 130, 77
+    a = inputs.random_keys(np.uint64, stride * count, seed=4)
+    got = run_fixed(a, n, count, stride)
+    assert (got == oracle.sort_fixed(a, n, count, stride)).all()
+    assert (run_fixed(a, n, count, stride) == got).all()
