@@ -1,0 +1,595 @@
+// Segmented (CSR) sorting of ragged batches: segment i is
+// keys[offsets[i], offsets[i+1]), sizes 0..256, with an optional uint32
+// payload permuted with the keys.
+//
+// The paper's future-work proposal (Section 5) is to bucket the base cases by
+// size and solve batches of subproblems of identical size.  That is what
+// happens here, entirely on the device:
+//
+//   count    each block histograms the size classes of its segments
+//   scan     one block turns the per-block histograms into class totals,
+//            class start offsets and per-block output bases; zeroes the tile
+//            counter
+//   scatter  each block writes its segment ids into the class lists (segment
+//            ids grouped by class; no contended atomics)
+//   sort     one persistent launch: every wave repeatedly claims a tile of
+//            one class (atomic counter, classes ordered from most to least
+//            work per tile) and runs that class's handler:
+//              sizes 2..16: one segment per lane, the network of exactly that
+//                           size in registers;
+//              17..64 / 65..128 / 129..256: Register Sample Sort with 16-,
+//                           32- or 64-lane groups (rss.hpp), several rounds
+//                           of groups per tile.
+//
+// Size classes: 0..14 = sizes 2..16, 15 = 17..64, 16 = 65..128, 17 = 129..256.
+// Sizes 0 and 1 need no work.  A segment longer than 256 keys or with a
+// negative size is skipped and flagged in the status word.
+//
+// Modes: the four kernels replayed from a cached hipGraph (the graph is
+// captured once per key type / payload / network family; each call only
+// rewrites the kernel arguments of its nodes), the same four launched
+// directly, or the "plain" baseline: count/scan/scatter, a copy of the class
+// counts to the host, then one ordinary launch per non-empty class.
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+#include "rss.hpp"
+
+namespace ss {
+
+constexpr int kClasses = 18;
+constexpr int kNetClasses = 15;
+constexpr int kBinThreads = 256;
+constexpr int kBinItems = 4;                       // segments per thread per chunk
+constexpr int kBinChunk = kBinThreads * kBinItems;  // segments per block iteration
+constexpr int kBinBlocks = 1024;                   // fixed grid of count/scatter
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;
+
+// ctrl layout (uint32 words)
+constexpr int kCtrlCount = 0;        // [kClasses] segments per class
+constexpr int kCtrlStart = 32;       // [kClasses] start of each class list
+constexpr int kCtrlTile = 64;        // tile counter of the persistent kernel
+constexpr int kCtrlWords = 128;
+
+__device__ __forceinline__ int size_class(int sz) {
+  if (sz < 2) return sz >= 0 ? -1 : -3;  // -1: nothing to do, -3: bad offsets
+  if (sz <= 16) return sz - 2;
+  if (sz <= 64) return 15;
+  if (sz <= 128) return 16;
+  if (sz <= kMaxN) return 17;
+  return -2;  // too big
+}
+
+// Tile size (segments) of a class; rounds = RSS group rounds per tile.
+__host__ __device__ __forceinline__ int class_tile(int c, int rounds) {
+  if (c < kNetClasses) return kWave;
+  const int groups = c == 15 ? 4 : (c == 16 ? 2 : 1);
+  return groups * rounds;
+}
+
+// Classes in the order the persistent kernel hands out tiles.
+__host__ __device__ __forceinline__ int class_at(int order) {
+  return order < 3 ? 17 - order : 14 - (order - 3);
+}
+
+// --- binning ---------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBinThreads)
+seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg, uint32_t* __restrict__ blockhist,
+                 int* status) {
+  __shared__ uint32_t hist[kClasses];
+  if (threadIdx.x < kClasses) hist[threadIdx.x] = 0;
+  __syncthreads();
+  int bad = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBinChunk; base < nseg; base += (int64_t)gridDim.x * kBinChunk) {
+#pragma unroll
+    for (int q = 0; q < kBinItems; ++q) {
+      const int64_t i = base + q * kBinThreads + threadIdx.x;
+      if (i < nseg) {
+        const int c = size_class(offsets[i + 1] - offsets[i]);
+        if (c >= 0)
+          atomicAdd(&hist[c], 1u);
+        else if (c < -1)
+          bad = c == -2 ? kStatusTooBig : kStatusInval;
+      }
+    }
+  }
+  if (bad) report(status, bad);
+  __syncthreads();
+  if (threadIdx.x < kClasses) blockhist[threadIdx.x * kBinBlocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+// One block of 1024 threads: class totals, class starts, per-block bases
+// (written over the per-block histogram), tile counter reset.  The histogram
+// is laid out [class][block]; one wave scans one class row of kBinBlocks
+// values, 16 per lane.
+__global__ void __launch_bounds__(1024)
+seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restrict__ ctrl) {
+  constexpr int kPerLane = kBinBlocks / kWave;
+  __shared__ uint32_t tot[kClasses];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  (void)nblocks;
+  for (int c = wave; c < kClasses; c += 1024 / kWave) {
+    uint32_t* row = blockhist + c * kBinBlocks + lane * kPerLane;
+    uint32_t v[kPerLane];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+      v[i] = row[i];
+      sum += v[i];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+      if (lane >= d) incl += y;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+      row[i] = run;
+      run += v[i];
+    }
+    if (lane == kWave - 1) tot[c] = incl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t st = 0;
+    for (int c = 0; c < kClasses; ++c) {
+      ctrl[kCtrlCount + c] = tot[c];
+      ctrl[kCtrlStart + c] = st;
+      st += tot[c];
+    }
+    ctrl[kCtrlTile] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBinThreads)
+seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint32_t* __restrict__ blockbase,
+                   const uint32_t* __restrict__ ctrl, int32_t* __restrict__ ids) {
+  __shared__ uint32_t cur[kClasses];
+  if (threadIdx.x < kClasses)
+    cur[threadIdx.x] = ctrl[kCtrlStart + threadIdx.x] + blockbase[threadIdx.x * kBinBlocks + blockIdx.x];
+  __syncthreads();
+  for (int64_t base = (int64_t)blockIdx.x * kBinChunk; base < nseg; base += (int64_t)gridDim.x * kBinChunk) {
+#pragma unroll
+    for (int q = 0; q < kBinItems; ++q) {
+      const int64_t i = base + q * kBinThreads + threadIdx.x;
+      if (i < nseg) {
+        const int c = size_class(offsets[i + 1] - offsets[i]);
+        if (c >= 0) ids[atomicAdd(&cur[c], 1u)] = (int32_t)i;
+      }
+    }
+  }
+}
+
+// --- tile handlers -----------------------------------------------------------
+
+template <int F, int N, class K, bool V>
+__device__ __forceinline__ void net_tile(K* __restrict__ keys, uint32_t* __restrict__ vals,
+                                         const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
+                                         int list, int count, int first, K flip) {
+  const int j = first + lane_id();
+  if (j >= count) return;
+  const int seg = ids[list + j];
+  K* p = keys + offsets[seg];
+  K r[N];
+  uint32_t v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = p[i] ^ flip;
+  if constexpr (V) {
+    uint32_t* pv = vals + offsets[seg];
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = pv[i];
+    net_sort<F, N>(r, v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) pv[i] = v[i];
+  } else {
+    net_sort<F, N>(r);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) p[i] = r[i] ^ flip;
+}
+
+template <int F, class K, bool V>
+__device__ __forceinline__ void net_tile_dispatch(int n, K* keys, uint32_t* vals, const int32_t* offsets,
+                                                  const int32_t* ids, int list, int count, int first, K flip) {
+  switch (n) {
+    case 2: net_tile<F, 2, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 3: net_tile<F, 3, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 4: net_tile<F, 4, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 5: net_tile<F, 5, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 6: net_tile<F, 6, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 7: net_tile<F, 7, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 8: net_tile<F, 8, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 9: net_tile<F, 9, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 10: net_tile<F, 10, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 11: net_tile<F, 11, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 12: net_tile<F, 12, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 13: net_tile<F, 13, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 14: net_tile<F, 14, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    case 15: net_tile<F, 15, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+    default: net_tile<F, 16, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+  }
+}
+
+// Per-wave LDS big enough for any RSS group layout of this key type.
+template <class K, bool V> struct WaveLds {
+  static constexpr size_t kBytes16 = 4 * sizeof(GroupLds<K, V, 16>);
+  static constexpr size_t kBytes32 = 2 * sizeof(GroupLds<K, V, 32>);
+  static constexpr size_t kBytes64 = sizeof(GroupLds<K, V, 64>);
+  static constexpr size_t kBytes = kBytes16 > kBytes32 ? (kBytes16 > kBytes64 ? kBytes16 : kBytes64)
+                                                       : (kBytes32 > kBytes64 ? kBytes32 : kBytes64);
+};
+
+template <int F, class K, bool V, int G>
+__device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint32_t* vals,
+                                         const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
+                                         int list, int count, int first, int rounds, K flip, int k0) {
+  constexpr int kGroups = kWave / G;
+  auto* L = reinterpret_cast<GroupLds<K, V, G>*>(wave_lds);
+  const int g = lane_id() / G;
+  for (int r = 0; r < rounds; ++r) {
+    const int j = first + r * kGroups + g;
+    int m = 0;
+    int64_t lo = 0;
+    if (j < count) {
+      const int seg = ids[list + j];
+      lo = offsets[seg];
+      m = offsets[seg + 1] - (int)lo;
+    }
+    rss_group_sort<F, K, V, G>(L[g], keys + lo, V ? vals + lo : nullptr, m, flip, k0);
+  }
+}
+
+struct SortArgs {
+  const int32_t* offsets;
+  const int32_t* ids;
+  const uint32_t* ctrl;
+  int rounds;
+  int k0[3];
+};
+
+// Runs tile `tile_in_class` of class c.
+template <int F, class K, bool V>
+__device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint32_t* vals, const SortArgs& a,
+                                         K flip, int c, int tile_in_class, int count, int list) {
+  const int first = tile_in_class * class_tile(c, a.rounds);
+  if (c < kNetClasses) {
+    net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
+  } else if (c == 15) {
+    rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[0]);
+  } else if (c == 16) {
+    rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[1]);
+  } else {
+    rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[2]);
+  }
+}
+
+// Persistent kernel: waves claim tiles until all are done.
+template <int F, class K, bool V>
+__global__ void __launch_bounds__(kSortThreads)
+seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip,
+                      int chunk) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][WaveLds<K, V>::kBytes];
+  const int wave = threadIdx.x / kWave;
+  // tile prefix over classes in hand-out order (wave-uniform values)
+  int ntiles[kClasses];
+  int total = 0;
+#pragma unroll
+  for (int o = 0; o < kClasses; ++o) {
+    const int c = class_at(o);
+    const int cnt = (int)a.ctrl[kCtrlCount + c];
+    const int ts = class_tile(c, a.rounds);
+    ntiles[o] = (cnt + ts - 1) / ts;
+    total += ntiles[o];
+  }
+  while (true) {
+    int t0 = 0;
+    if (lane_id() == 0) t0 = (int)atomicAdd(&ctrl[kCtrlTile], (uint32_t)chunk);
+    t0 = __builtin_amdgcn_readfirstlane(t0);
+    if (t0 >= total) break;
+    const int t1 = min(t0 + chunk, total);
+    for (int t = t0; t < t1; ++t) {
+      int c = 0, base = 0, acc = 0;
+#pragma unroll
+      for (int o = 0; o < kClasses; ++o) {
+        if (t >= acc && t < acc + ntiles[o]) {
+          c = class_at(o);
+          base = acc;
+        }
+        acc += ntiles[o];
+      }
+      run_tile<F, K, V>(lds[wave], keys, vals, a, flip, c, t - base, (int)a.ctrl[kCtrlCount + c],
+                        (int)a.ctrl[kCtrlStart + c]);
+    }
+  }
+}
+
+// Plain baseline: one launch per class, tile = blockIdx * waves + wave.
+template <int F, class K, bool V>
+__global__ void __launch_bounds__(kSortThreads)
+seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, K flip, int c, int count,
+                 int list) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][WaveLds<K, V>::kBytes];
+  const int wave = threadIdx.x / kWave;
+  const int tile = blockIdx.x * kSortWaves + wave;
+  run_tile<F, K, V>(lds[wave], keys, vals, a, flip, c, tile, count, list);
+}
+
+// --- host side ---------------------------------------------------------------
+
+struct GraphEntry {
+  int key = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t nodes[4] = {nullptr, nullptr, nullptr, nullptr};  // count, scan, scatter, sort
+  int persist_blocks = 0;
+};
+
+struct SegmentedCache {
+  std::mutex mu;
+  int32_t* ids = nullptr;
+  int64_t ids_cap = 0;
+  uint32_t* ctrl = nullptr;
+  uint32_t* blockhist = nullptr;
+  uint32_t* host_ctrl = nullptr;  // pinned, for the plain baseline
+  hipStream_t capture_stream = nullptr;
+  std::vector<GraphEntry> graphs;
+};
+
+static hipError_t ensure_workspace(DeviceCtx* c, int32_t nseg) {
+  SegmentedCache* s = c->seg;
+  hipError_t e = hipSuccess;
+  if (!s->ctrl) {
+    e = hipMalloc(&s->ctrl, kCtrlWords * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->blockhist, kBinBlocks * kClasses * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&s->host_ctrl, kCtrlWords * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  if (s->ids_cap < nseg) {
+    // growing: wait for in-flight users of the old list before freeing it
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess && s->ids) e = hipFree(s->ids);
+    s->ids = nullptr;
+    s->ids_cap = 0;
+    int64_t cap = nseg < 1024 ? 1024 : (int64_t)nseg + nseg / 4;
+    if (cap > 0x7FFFFFFF) cap = 0x7FFFFFFF;
+    if (e == hipSuccess) e = hipMalloc(&s->ids, cap * sizeof(int32_t));
+    if (e != hipSuccess) return e;
+    s->ids_cap = cap;
+  }
+  return hipSuccess;
+}
+
+template <int F, class K, bool V>
+static int persistent_blocks(DeviceCtx* c) {
+  int occ = tuning().persist_occ;
+  if (occ <= 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_persistent_kernel<F, K, V>, kSortThreads, 0) !=
+            hipSuccess ||
+        nb <= 0)
+      nb = 2;
+    occ = nb;
+  }
+  return occ * c->num_cus;
+}
+
+static SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
+  SortArgs a;
+  a.offsets = offsets;
+  a.ids = s->ids;
+  a.ctrl = s->ctrl;
+  a.rounds = tuning().rss_rounds;
+  a.k0[0] = tuning().rss_k[0];
+  a.k0[1] = tuning().rss_k[1];
+  a.k0[2] = tuning().rss_k[2];
+  return a;
+}
+
+// The four kernels with their arguments, as launch parameter blocks.
+template <int F, class K, bool V>
+struct SegLaunch {
+  // argument storage (addresses handed to HIP)
+  const int32_t* offsets;
+  int32_t nseg;
+  uint32_t* blockhist;
+  int* status;
+  int nblocks;
+  uint32_t* ctrl;
+  const uint32_t* ctrl_c;
+  const uint32_t* blockbase;
+  int32_t* ids;
+  K* keys;
+  uint32_t* vals;
+  SortArgs args;
+  K flip;
+  int chunk;
+  void* p_count[4];
+  void* p_scan[3];
+  void* p_scatter[5];
+  void* p_sort[6];
+  int persist_blocks;
+
+  void fill(DeviceCtx* c, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
+    SegmentedCache* s = c->seg;
+    offsets = off;
+    nseg = n;
+    blockhist = s->blockhist;
+    status = c->status;
+    nblocks = kBinBlocks;
+    ctrl = s->ctrl;
+    ctrl_c = s->ctrl;
+    blockbase = s->blockhist;
+    ids = s->ids;
+    keys = k;
+    vals = v;
+    args = make_args(off, s);
+    flip = fl;
+    chunk = tuning().tile_chunk;
+    p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status;
+    p_scan[0] = &blockhist; p_scan[1] = &nblocks; p_scan[2] = &ctrl;
+    p_scatter[0] = &offsets; p_scatter[1] = &nseg; p_scatter[2] = &blockbase; p_scatter[3] = &ctrl_c;
+    p_scatter[4] = &ids;
+    p_sort[0] = &keys; p_sort[1] = &vals; p_sort[2] = &args; p_sort[3] = &ctrl; p_sort[4] = &flip;
+    p_sort[5] = &chunk;
+  }
+
+  hipKernelNodeParams node(int i) {
+    hipKernelNodeParams p{};
+    p.sharedMemBytes = 0;
+    p.extra = nullptr;
+    switch (i) {
+      case 0:
+        p.func = (void*)seg_count_kernel;
+        p.gridDim = dim3(kBinBlocks);
+        p.blockDim = dim3(kBinThreads);
+        p.kernelParams = p_count;
+        break;
+      case 1:
+        p.func = (void*)seg_scan_kernel;
+        p.gridDim = dim3(1);
+        p.blockDim = dim3(1024);
+        p.kernelParams = p_scan;
+        break;
+      case 2:
+        p.func = (void*)seg_scatter_kernel;
+        p.gridDim = dim3(kBinBlocks);
+        p.blockDim = dim3(kBinThreads);
+        p.kernelParams = p_scatter;
+        break;
+      default:
+        p.func = (void*)seg_persistent_kernel<F, K, V>;
+        p.gridDim = dim3(persist_blocks);
+        p.blockDim = dim3(kSortThreads);
+        p.kernelParams = p_sort;
+        break;
+    }
+    return p;
+  }
+
+  hipError_t launch_binning(hipStream_t s) {
+    hipLaunchKernelGGL(seg_count_kernel, dim3(kBinBlocks), dim3(kBinThreads), 0, s, offsets, nseg, blockhist,
+                       status);
+    hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, blockhist, nblocks, ctrl);
+    hipLaunchKernelGGL(seg_scatter_kernel, dim3(kBinBlocks), dim3(kBinThreads), 0, s, offsets, nseg, blockbase,
+                       ctrl_c, ids);
+    return hipGetLastError();
+  }
+  hipError_t launch_direct(hipStream_t s) {
+    hipError_t e = launch_binning(s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((seg_persistent_kernel<F, K, V>), dim3(persist_blocks), dim3(kSortThreads), 0, s, keys,
+                       vals, args, ctrl, flip, chunk);
+    return hipGetLastError();
+  }
+};
+
+template <int F, class K, bool V>
+static hipError_t run_plain(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) {
+  SegmentedCache* sc = c->seg;
+  hipError_t e = L.launch_binning(s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, kCtrlWords * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int o = 0; o < kClasses; ++o) {
+    const int cls = class_at(o);
+    const int count = (int)sc->host_ctrl[kCtrlCount + cls];
+    if (count == 0) continue;
+    const int ts = class_tile(cls, L.args.rounds);
+    const int tiles = (count + ts - 1) / ts;
+    const int blocks = (tiles + kSortWaves - 1) / kSortWaves;
+    hipLaunchKernelGGL((seg_class_kernel<F, K, V>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
+                       L.args, L.flip, cls, count, (int)sc->host_ctrl[kCtrlStart + cls]);
+  }
+  return hipGetLastError();
+}
+
+template <int F, class K, bool V>
+static hipError_t run_graph(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) {
+  SegmentedCache* sc = c->seg;
+  const int key = (int)sizeof(K) * 4 + (V ? 2 : 0) + F;
+  GraphEntry* g = nullptr;
+  for (GraphEntry& ge : sc->graphs)
+    if (ge.key == key && ge.persist_blocks == L.persist_blocks) g = &ge;
+  hipError_t e = hipSuccess;
+  if (!g) {
+    GraphEntry ne;
+    ne.key = key;
+    ne.persist_blocks = L.persist_blocks;
+    e = hipGraphCreate(&ne.graph, 0);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      hipKernelNodeParams p = L.node(i);
+      e = hipGraphAddKernelNode(&ne.nodes[i], ne.graph, i ? &ne.nodes[i - 1] : nullptr, i ? 1 : 0, &p);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ne.exec, ne.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (ne.graph) (void)hipGraphDestroy(ne.graph);
+      return e;
+    }
+    sc->graphs.push_back(ne);
+    g = &sc->graphs.back();
+  } else {
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      hipKernelNodeParams p = L.node(i);
+      e = hipGraphExecKernelNodeSetParams(g->exec, g->nodes[i], &p);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipGraphLaunch(g->exec, s);
+}
+
+template <int F, class K, bool V>
+static int segmented_impl(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, K flip,
+                          int mode, hipStream_t s) {
+  SegLaunch<F, K, V> L;
+  L.persist_blocks = persistent_blocks<F, K, V>(c);
+  L.fill(c, keys, vals, offsets, nseg, flip);
+  hipError_t e;
+  if (mode == 2)
+    e = run_plain(c, L, s);
+  else if (mode == 1)
+    e = L.launch_direct(s);
+  else
+    e = run_graph(c, L, s);
+  if (e == hipErrorOutOfMemory) return -5;
+  return e == hipSuccess ? 0 : -4;
+}
+
+template <class K>
+static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, K flip,
+                         int mode, hipStream_t s) {
+  {
+    {
+      static std::mutex create_mu;
+      std::lock_guard<std::mutex> lock(create_mu);
+      if (!c->seg) c->seg = new SegmentedCache();
+    }
+    std::lock_guard<std::mutex> lock(c->seg->mu);
+    hipError_t e = ensure_workspace(c, nseg);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? -5 : -4;
+    const bool fam = tuning().family == 1;
+    if (vals)
+      return fam ? segmented_impl<1, K, true>(c, keys, vals, offsets, nseg, flip, mode, s)
+                 : segmented_impl<0, K, true>(c, keys, vals, offsets, nseg, flip, mode, s);
+    return fam ? segmented_impl<1, K, false>(c, keys, vals, offsets, nseg, flip, mode, s)
+               : segmented_impl<0, K, false>(c, keys, vals, offsets, nseg, flip, mode, s);
+  }
+}
+
+int segmented_u32(DeviceCtx* c, uint32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                  uint32_t flip, int mode, hipStream_t s) {
+  return segmented_any<uint32_t>(c, keys, vals, offsets, nseg, flip, mode, s);
+}
+int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                  uint64_t flip, int mode, hipStream_t s) {
+  return segmented_any<uint64_t>(c, keys, vals, offsets, nseg, flip, mode, s);
+}
+
+}  // namespace ss

@@ -1,0 +1,188 @@
+"""Parity of the segmented (CSR, ragged) sorts with the CPU oracle, in all three modes."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2002_05599_amd as ss
+from paper_2002_05599_amd import inputs
+from helpers import first_mismatch, from_dev, pairs_multiset_equal, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TYPES = [np.uint32, np.int32, np.uint64, np.int64]
+MODES = [ss.MODE_AUTO, ss.MODE_PERSISTENT, ss.MODE_PLAIN]
+MODE_IDS = ["graph", "persistent", "plain"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    ss.lib()
+    yield
+
+
+def run_seg(keys, off, vals=None, mode=ss.MODE_AUTO):
+    tk = to_dev(keys)
+    to = to_dev(off)
+    tv = to_dev(vals) if vals is not None else None
+    ss.segmented_sort(tk, to, tv, mode=mode)
+    return from_dev(tk), (from_dev(tv) if tv is not None else None)
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("dtype", TYPES, ids=lambda d: np.dtype(d).name)
+def test_mixed_sizes_keys_only(dtype, mode):
+    rng = np.random.default_rng(5)
+    sizes = np.concatenate([np.arange(0, 257), rng.integers(0, 257, size=700), rng.integers(0, 17, size=900)])
+    rng.shuffle(sizes)
+    off = inputs.offsets_from_sizes(sizes) + 3  # offsets need not start at 0
+    keys = inputs.random_keys(dtype, int(off[-1]) + 5, seed=21)
+    got, _ = run_seg(keys, off, mode=mode)
+    want, _ = oracle.sort_segments(keys, off)
+    assert (got == want).all(), first_mismatch(got, want)
+    assert ss.device_status() == 0
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+@pytest.mark.parametrize("dtype", TYPES, ids=lambda d: np.dtype(d).name)
+def test_payload_distinct_keys_exact(dtype, mode):
+    sizes = inputs.geometric_sizes(6000, seed=8)
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    keys = inputs.distinct_u64(total, seed=8)
+    if np.dtype(dtype).itemsize == 4:
+        # distinct 32-bit keys: a permutation of a random distinct set
+        keys = (np.random.default_rng(8).permutation(np.arange(total, dtype=np.int64) * 7919 + 13)
+                & 0xFFFFFFFF).astype(np.uint32)
+        assert np.unique(keys).size == total
+    keys = keys.view(dtype) if keys.dtype.itemsize == np.dtype(dtype).itemsize else keys.astype(dtype)
+    vals = inputs.segment_index_payload(off)
+    gk, gv = run_seg(keys, off, vals, mode=mode)
+    wk, wv = oracle.sort_segments(keys, off, vals)
+    assert (gk == wk).all(), first_mismatch(gk, wk)
+    assert (gv == wv).all(), first_mismatch(gv, wv)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.int64], ids=lambda d: np.dtype(d).name)
+def test_payload_duplicate_keys_multiset(dtype):
+    rng = np.random.default_rng(9)
+    sizes = rng.integers(0, 257, size=1500)
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    keys = rng.integers(0, 5, size=total).astype(dtype)
+    info = np.iinfo(dtype)
+    keys[rng.random(total) < 0.1] = info.max  # collides with the padding value
+    vals = np.arange(total, dtype=np.uint32)
+    gk, gv = run_seg(keys, off, vals)
+    wk, wv = oracle.sort_segments(keys, off, vals)
+    assert (gk == wk).all()
+    bad = pairs_multiset_equal(gk, gv, keys, vals, off)
+    assert bad is None, f"segment {bad}: payload is not a permutation of its pairs"
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_config3_shape_small(dist):
+    keys, off = inputs.config3(nseg=4000, dist=dist, seed=3)
+    for mode in MODES:
+        got, _ = run_seg(keys, off, mode=mode)
+        want, _ = oracle.sort_segments(keys, off)
+        assert (got == want).all(), (mode, first_mismatch(got, want))
+
+
+def test_config4_shape_small_all_modes_agree():
+    keys, vals, off = inputs.config4(nseg=30000, seed=4)
+    wk, wv = oracle.sort_segments(keys, off, vals)
+    for mode in MODES:
+        gk, gv = run_seg(keys, off, vals, mode=mode)
+        assert (gk == wk).all() and (gv == wv).all(), mode
+
+
+def test_oversize_and_bad_offsets_flagged():
+    sizes = np.array([5, 300, 20, 0, 1, 256])
+    off = inputs.offsets_from_sizes(sizes)
+    keys = inputs.random_keys(np.uint32, int(off[-1]), seed=1)
+    got, _ = run_seg(keys, off)
+    assert ss.device_status() == -3
+    assert ss.device_status() == 0  # reading clears it
+    want, _ = oracle.sort_segments(keys, off)
+    lo, hi = off[1], off[2]
+    assert (got[lo:hi] == keys[lo:hi]).all(), "oversize segment must be left untouched"
+    mask = np.ones(keys.size, bool)
+    mask[lo:hi] = False
+    assert (got[mask] == want[mask]).all()
+    # decreasing offsets
+    off2 = np.array([0, 10, 4, 30], dtype=np.int32)
+    keys2 = inputs.random_keys(np.uint32, 30, seed=2)
+    run_seg(keys2, off2)
+    assert ss.device_status() == -1
+
+
+def test_empty_and_trivial_batches():
+    assert ss.device_status() == 0
+    got, _ = run_seg(np.arange(10, dtype=np.uint32)[::-1].copy(), np.array([0], dtype=np.int32))
+    assert (got == np.arange(10)[::-1]).all()
+    got, _ = run_seg(np.array([3, 1, 2], dtype=np.int64), np.array([0, 1, 2, 3], dtype=np.int32))
+    assert (got == [3, 1, 2]).all()
+
+
+def test_graph_replays_with_changing_inputs():
+    """The cached graph is replayed with new buffers, sizes and shapes; eager work in between."""
+    import torch
+    for rep in range(5):
+        nseg = [1000, 1000, 4000, 10, 2500][rep]
+        keys, vals, off = inputs.config4(nseg=nseg, seed=40 + rep)
+        tk, tv, to = to_dev(keys), to_dev(vals), to_dev(off)
+        ss.segmented_sort(tk, to, tv, mode=ss.MODE_AUTO)
+        scratch = torch.ones(1 << 20, device="cuda").sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        del scratch
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (from_dev(tk) == wk).all() and (from_dev(tv) == wv).all(), rep
+
+
+def test_repeat_runs_identical():
+    keys, off = inputs.config3(nseg=3000, dist="zipf", seed=12)
+    r1, _ = run_seg(keys, off)
+    r2, _ = run_seg(keys, off)
+    assert (r1 == r2).all()
+
+
+def _check_sampled(got_k, keys, off, got_v=None, vals=None, nsample=4000):
+    rng = np.random.default_rng(0)
+    nseg = off.size - 1
+    segs = np.unique(np.concatenate([rng.integers(0, nseg, size=nsample), [0, nseg - 1]]))
+    for i in segs:
+        lo, hi = int(off[i]), int(off[i + 1])
+        wk, wv = oracle.sort_one(keys[lo:hi], None if vals is None else vals[lo:hi])
+        assert (got_k[lo:hi] == wk).all(), f"segment {i}"
+        if vals is not None:
+            assert (got_v[lo:hi] == wv).all(), f"segment {i} payload"
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_config3_full_size_sampled(dist):
+    """2^20 CSR arrays of 17..256 int32 keys: sampled segments vs the oracle + invariants."""
+    keys, off = inputs.config3(dist=dist)
+    got, _ = run_seg(keys, off)
+    assert ss.device_status() == 0
+    _check_sampled(got, keys, off)
+    # every segment sorted; multiset fingerprint per batch
+    d = got[1:].astype(np.int64) - got[:-1].astype(np.int64)
+    boundary = np.zeros(got.size - 1, bool)
+    boundary[off[1:-1] - 1] = True
+    assert ((d >= 0) | boundary).all()
+    assert np.sort(got, kind="stable").tobytes() == np.sort(keys, kind="stable").tobytes()
+
+
+@pytest.mark.slow
+def test_config4_full_size_sampled():
+    """10^7 ragged segments, u64 distinct keys + u32 payload (the bench batch)."""
+    keys, vals, off = inputs.config4()
+    gk, gv = run_seg(keys, off, vals)
+    assert ss.device_status() == 0
+    _check_sampled(gk, keys, off, gv, vals)
+    # payload is the in-segment index: it must index the original segment
+    seg_start = np.repeat(off[:-1], np.diff(off)).astype(np.int64)
+    assert (keys[seg_start + gv.astype(np.int64)] == gk).all()
