@@ -86,6 +86,42 @@ def cpu_baseline_fixed(n, dtype, seconds):
                       f"{threads} host threads, {el:.1f} s"}
 
 
+class StepBuffers:
+    """``count`` device copies of a pristine input, restored (untimed) on demand."""
+
+    def __init__(self, pristine, count):
+        self.pristine = pristine
+        self.bufs = [tuple(t.clone() for t in pristine) for _ in range(count)]
+
+    def restore(self):
+        import torch
+        for b in self.bufs:
+            for dst, src in zip(b, self.pristine):
+                dst.copy_(src)
+        torch.cuda.synchronize()
+
+
+def time_steps(step, bufs, steps, warmup):
+    """Run warmup steps, restore every copy, then time exactly ``steps`` steps
+    (one fresh copy each) between two synchronisations and two events."""
+    import torch
+    for i in range(warmup):
+        step(bufs.bufs[i % len(bufs.bufs)])
+    bufs.restore()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for i in range(steps):
+        step(bufs.bufs[i])
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / steps, wall
+
+
 def bench_fixed(args):
     import torch
     import paper_2002_05599_amd as ss
@@ -94,25 +130,12 @@ def bench_fixed(args):
     n = args.n
     count = 1 << args.count_log2
     keys = torch.from_numpy(inputs.fixed_keys(np.uint32, n, count, "uniform", seed=2)).cuda()
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        ss.sort_small(keys, n)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        ss.sort_small(keys, n)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / args.steps
+    bufs = StepBuffers((keys,), args.steps)
+    ms, wall = time_steps(lambda b: ss.sort_small(b[0], n), bufs, args.steps, args.warmup)
     nkeys = count * n
     algo_bytes = 2 * nkeys * 4
     achieved = algo_bytes / (ms * 1e-3) / 1e9
     kkey = f"fixed_tile_kernel<n={n},u32>"
-    tb = traffic_for(kkey)
     out = {
         "metric": "keys/s", "value": nkeys / (ms * 1e-3), "unit": "keys/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -121,10 +144,57 @@ def bench_fixed(args):
         "config": {"workload": f"batched network sort, 2^{args.count_log2} arrays x n={n} uint32, "
                                f"uniform, stride {n}", "n": n, "count": count, "key": "uint32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(kkey),
                      "kernel": kkey, "algorithmic_bytes_per_launch": algo_bytes},
     }
     return out, (n, np.uint32)
+
+
+def seg_bytes(total, nseg, key_bytes, has_vals):
+    return 2 * total * (key_bytes + (4 if has_vals else 0)) + 4 * (nseg + 1)
+
+
+def bench_rss(args, dist="uniform", nseg=1 << 20):
+    import torch
+    import paper_2002_05599_amd as ss
+    from paper_2002_05599_amd import inputs
+
+    keys, off = inputs.config3(nseg=nseg, dist=dist)
+    total = int(off[-1])
+    tk = torch.from_numpy(keys).cuda()
+    to = torch.from_numpy(off).cuda()
+    bufs = StepBuffers((tk,), args.steps)
+    res = {}
+    for name, mode in (("graph", ss.MODE_AUTO), ("plain", ss.MODE_PLAIN)):
+        ms, wall = time_steps(lambda b: ss.segmented_sort(b[0], to, mode=mode), bufs, args.steps, args.warmup)
+        gbs = seg_bytes(total, nseg, 4, False) / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "keys_per_s": total / (ms * 1e-3), "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    assert ss.device_status() == 0
+    return {"workload": f"RSS, {nseg} CSR arrays, n uniform in [17,256], int32 {dist}", "keys": total,
+            "nseg": nseg, **res}
+
+
+def bench_ragged(args, nseg=10_000_000):
+    import torch
+    import paper_2002_05599_amd as ss
+    from paper_2002_05599_amd import inputs
+
+    keys, vals, off = inputs.config4(nseg=nseg)
+    total = int(off[-1])
+    tk = torch.from_numpy(keys).cuda()
+    tv = torch.from_numpy(vals).cuda()
+    to = torch.from_numpy(off).cuda()
+    bufs = StepBuffers((tk, tv), args.steps)
+    res = {}
+    for name, mode in (("graph", ss.MODE_AUTO), ("persistent", ss.MODE_PERSISTENT), ("plain", ss.MODE_PLAIN)):
+        ms, wall = time_steps(lambda b: ss.segmented_sort(b[0], to, b[1], mode=mode), bufs, args.steps,
+                              args.warmup)
+        gbs = seg_bytes(total, nseg, 8, True) / (ms * 1e-3) / 1e9
+        res[name] = {"ms": ms, "keys_per_s": total / (ms * 1e-3), "GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    assert ss.device_status() == 0
+    res["graph_speedup_vs_plain"] = res["plain"]["ms"] / res["graph"]["ms"]
+    return {"workload": f"ragged, {nseg} segments, geometric sizes (mean 24, 1..256), uint64 distinct keys "
+                        f"+ uint32 payload", "keys": total, "nseg": nseg, **res}
 
 
 def main():
@@ -137,9 +207,12 @@ def main():
         out, (n, dt) = bench_fixed(args)
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline_fixed(n, dt, args.cpu_seconds)
+    elif args.workload == "rss":
+        out = {"rss_uniform": bench_rss(args, "uniform"), "rss_zipf": bench_rss(args, "zipf")}
+    elif args.workload == "ragged":
+        out = bench_ragged(args)
     else:
-        from paper_2002_05599_amd import benchmarks
-        out = benchmarks.run(args)
+        raise SystemExit(f"workload {args.workload} not available yet")
     print(json.dumps(out), flush=True)
 
 

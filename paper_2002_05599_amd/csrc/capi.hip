@@ -137,6 +137,7 @@ static std::vector<TuneEntry> tune_table() {
       {"tile_chunk", &t.tile_chunk, 1, 64, false},
       {"persist_occ", &t.persist_occ, 0, 16, false},
       {"rss_rounds", &t.rss_rounds, 1, 16, false},
+      {"interleave", &t.interleave, 0, 1, false},
   };
 }
 

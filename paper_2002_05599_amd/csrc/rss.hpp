@@ -4,12 +4,13 @@
 // The array is staged in LDS.  Each level of the recursion handles every
 // pending bucket (more than 16 keys) of the array:
 //
-//   1. sample: one lane per pending bucket picks 16 keys at equidistant
-//      positions floor((2t+1)*size/32), t = 0..15, and sorts them with the
-//      16-channel network (Section 3: "the same sorting method can be used as
-//      for the base case");
-//   2. splitters: s_i = S_{a*i} for i = 1..k-1 with k buckets and
-//      oversampling a = 16/k (Section 3, basic sample sort);
+//   1. sample: one lane per pending bucket picks a*k keys at equidistant
+//      positions floor((2t+1)*size/(2ak)) and sorts them with the network of
+//      a*k channels (Section 3: the splitter sample is sorted by the base-case
+//      sorter); k buckets with oversampling a = 3 for k = 4 (the paper's
+//      "332"), a = 16/k for k = 8 and 16;
+//   2. splitters: s_i = S_{a*i} for i = 1..k-1 (Section 3, basic sample
+//      sort);
 //   3. classify: bucket j = #{splitters < e}, i.e. s_j < e <= s_{j+1}, found
 //      by descending the perfect splitter tree without branches: compare with
 //      the root, then keep either the left or the right subtree with selects
@@ -50,7 +51,11 @@ template <class K, bool V, int G> struct GroupLds {
   static constexpr int kMaxFin = kCap / 2;    // buckets with 2..16 keys
   K key[kCap];
   uint32_t val[V ? kCap : 1];
-  K sample[kMaxPend][16];
+  K sample[kMaxPend][16];          // sorted sample of each pending bucket
+  uint16_t cnt[kMaxPend][16];      // per (bucket, child): count, then child offset
+  uint8_t nextpb[kMaxPend][16];    // pending index of each child at the next level, or 0xFF
+  uint8_t deg[kMaxPend];           // all splitters of the bucket equal
+  uint8_t pb[kCap];                // pending bucket of each position, or 0xFF
   uint16_t pend_st[2][kMaxPend];
   uint16_t pend_sz[2][kMaxPend];
   uint16_t fin_st[kMaxFin];
@@ -140,110 +145,199 @@ __device__ __forceinline__ void finish_dispatch(GroupLds<K, V, G>& L, bool ok, i
   }
 }
 
-// One level of classification + scatter for the pending buckets, k = 2^LOGK.
-template <int LOGK, class K, bool V, int G>
-__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int cur, int np, int& nf, int& npn) {
+// Oversampling factor a for k buckets: the sample of a*k keys must fit one
+// network of at most 16 channels.  k = 4 uses a = 3 (12 samples), the
+// parameters the paper found best on most machines ("332", Section 4.5).
+__host__ __device__ constexpr int oversampling(int k) { return k == 4 ? 3 : 16 / k; }
+
+// Sample of NS = a*k keys at positions floor((2t+1)*size/(2*NS)) of each
+// pending bucket (one lane per bucket), sorted by the NS-channel network;
+// also clears the bucket's child counters and records whether all of its
+// k-1 splitters are equal.
+template <int F, int NS, class K, bool V, int G>
+__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np, int k, int a) {
+  const int gl = lane_id() % G;
+  if (gl < np) {
+    const int st = L.pend_st[cur][gl];
+    const int sz = L.pend_sz[cur][gl];
+    K smp[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) smp[t] = L.key[st + ((2 * t + 1) * sz) / (2 * NS)];
+    net_sort<F, NS>(smp);
+    K lo_s = smp[0], hi_s = smp[0];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      L.sample[gl][t] = smp[t];
+      if (t == a - 1) lo_s = smp[t];
+      if (t == a * (k - 1) - 1) hi_s = smp[t];
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) L.cnt[gl][t] = 0;
+    L.deg[gl] = lo_s == hi_s ? 1 : 0;
+  }
+}
+
+// #{i = 1..k-1 : s_i < e} for the splitters s_i = smp[A*i - 1] of a sorted
+// sample held in LDS: a branch-free binary search (the in-memory splitter
+// tree of super scalar sample sort that the paper's register tree replaces).
+template <int LOGK, int A, class K>
+__device__ __forceinline__ int lds_bucket(K e, const K* smp) {
+  int j = 0;
+#pragma unroll
+  for (int step = (1 << LOGK) / 2; step >= 1; step >>= 1) {
+    const K sp = smp[A * (j + step) - 1];
+    j += (sp < e) ? step : 0;
+  }
+  return j;
+}
+
+// Three-way split of a bucket whose splitters all equal v: {<v}, {==v}, {>v}.
+template <class K>
+__device__ __forceinline__ int three_way(K e, K v) {
+  return e < v ? 0 : (e == v ? 1 : 2);
+}
+
+// One level of the recursion for every pending bucket of the group at once
+// (k = 2^LOGK children per bucket).  kFirst: the single bucket [0, m) whose
+// splitters are held in registers and classified by the register tree; later
+// levels take each key's bucket from pb[] and search that bucket's sample in
+// LDS.
+//
+// Stable multisplit: in slot s the lanes hold positions gl + G*s, so the keys
+// of one pending bucket occupy a contiguous lane range.  A key's rank among
+// the keys with the same (bucket, child) is the running count cnt[b][c] plus
+// the number of lower lanes in the same range whose child index matches
+// (ballots of the child-index bits); the lowest such lane then advances
+// cnt[b][c].  Per bucket, the counts are scanned into child offsets, the
+// children are registered (finish list or next-level pending list, in
+// position order) and every key is written to bucket start + child offset +
+// rank, together with its next-level bucket id.
+template <int LOGK, bool kFirst, class K, bool V, int G>
+__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
   constexpr int k = 1 << LOGK;
-  constexpr int a = 16 / k;  // oversampling factor
+  constexpr int a = oversampling(k);
   const int lane = lane_id();
   const int gl = lane % G;
   const int gbase = lane - gl;
   const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
   const uint64_t below = (1ull << lane) - 1ull;
 
-  for (int p = 0; ballot(p < np) != 0ull; ++p) {
-    const bool active = p < np;
-    const int st = active ? (int)L.pend_st[cur][p] : 0;
-    const int sz = active ? (int)L.pend_sz[cur][p] : 0;
-    K spl[k - 1];
+  // level 0: splitters s_1..s_{k-1} in registers (paper, Section 3)
+  K spl[k - 1];
+  bool deg0 = false;
+  if constexpr (kFirst) {
 #pragma unroll
-    for (int i = 0; i < k - 1; ++i) spl[i] = active ? L.sample[p][a * (i + 1) - 1] : K(0);
-    const bool degenerate = active && spl[0] == spl[k - 2];
-    const int nch = degenerate ? 3 : k;
+    for (int i = 0; i < k - 1; ++i) spl[i] = np > 0 ? L.sample[0][a * (i + 1) - 1] : K(0);
+    deg0 = np > 0 && spl[0] == spl[k - 2];
+  }
 
-    K e[4];
-    uint32_t v[4];
-    int c[4];
-    bool ok[4];
+  K e[4];
+  uint32_t v[4];
+  int c[4], pbk[4];
+  uint32_t rk[4];
+  bool ok[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int i = gl + G * s;
-      ok[s] = active && i < sz;
-      e[s] = ok[s] ? L.key[st + i] : K(0);
-      if constexpr (V) v[s] = ok[s] ? L.val[st + i] : 0u;
-      int cc = classify<LOGK>(e[s], spl);
-      int cd = e[s] < spl[0] ? 0 : (e[s] == spl[0] ? 1 : 2);
-      c[s] = degenerate ? cd : cc;
+  for (int s = 0; s < 4; ++s) {
+    const int i = gl + G * s;
+    ok[s] = false;
+    c[s] = 0;
+    pbk[s] = 0;
+    rk[s] = 0;
+    if (ballot(i < m) == 0ull) continue;  // no group has keys in this slot
+    int pp = 0xFF;
+    if (i < m) pp = kFirst ? (np > 0 ? 0 : 0xFF) : (int)L.pb[i];
+    ok[s] = pp != 0xFF;
+    e[s] = ok[s] ? L.key[i] : K(0);
+    if constexpr (V) v[s] = ok[s] ? L.val[i] : 0u;
+    int cc;
+    uint64_t same_b;
+    if constexpr (kFirst) {
+      cc = deg0 ? three_way(e[s], spl[0]) : classify<LOGK>(e[s], spl);
+      same_b = gmask;
+    } else {
+      const int q = ok[s] ? pp : 0;
+      const K* smp = L.sample[q];
+      const bool dg = L.deg[q] != 0;
+      cc = dg ? three_way(e[s], smp[a - 1]) : lds_bucket<LOGK, a>(e[s], smp);
+      // lanes of this slot inside the bucket's position range
+      const int st = L.pend_st[cur][q];
+      const int sz = L.pend_sz[cur][q];
+      const int lo = min(max(st - G * s, 0), G);
+      const int hi = min(max(st + sz - G * s, 0), G);
+      const uint64_t hm = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+      const uint64_t lm = (1ull << lo) - 1ull;
+      same_b = (hm & ~lm) << gbase;
     }
+    c[s] = cc;
+    pbk[s] = pp;
+    uint64_t my = ballot(ok[s]) & gmask & same_b;
+#pragma unroll
+    for (int b = 0; b < LOGK; ++b) {
+      const uint64_t B = ballot(ok[s] && ((cc >> b) & 1));
+      my &= ((cc >> b) & 1) ? B : ~B;
+    }
+    const uint32_t r = (uint32_t)__popcll(my & below);
+    const uint32_t base = ok[s] ? (uint32_t)L.cnt[ok[s] ? pp : 0][cc] : 0u;
+    rk[s] = base + r;
+    if (ok[s] && r == 0) L.cnt[pp][cc] = (uint16_t)(base + (uint32_t)__popcll(my));
+    wave_lds_sync();
+  }
 
-    // stable multisplit: rank within slot, per-child running counts
-    uint32_t cnt = 0;
-    uint32_t pre[4];
-    uint32_t rank[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const uint64_t A = ballot(ok[s]) & gmask;
-      uint64_t my = A, mq = A;
-#pragma unroll
-      for (int b = 0; b < LOGK; ++b) {
-        const uint64_t B = ballot(ok[s] && ((c[s] >> b) & 1));
-        my &= ((c[s] >> b) & 1) ? B : ~B;
-        mq &= ((gl >> b) & 1) ? B : ~B;
-      }
-      rank[s] = (uint32_t)__popcll(my & below);
-      pre[s] = cnt;
-      cnt += (uint32_t)__popcll(mq);
-    }
-    // exclusive scan of the child counts over lanes gl < nch of the group
-    const uint32_t x = (gl < nch) ? cnt : 0u;
+  // scan each bucket's child counts into offsets; register the children
+  for (int r0 = 0; ballot(r0 < np * 16) != 0ull; r0 += G) {
+    const int q = r0 + gl;
+    const int pq = q >> 4;
+    const int cq = q & 15;
+    const bool okq = pq < np;
+    const bool dg = okq && L.deg[pq] != 0;
+    const int nchq = okq ? (dg ? 3 : k) : 0;
+    const bool own = cq < nchq;
+    const uint32_t x = own ? (uint32_t)L.cnt[pq][cq] : 0u;
     uint32_t incl = x;
 #pragma unroll
     for (int d = 1; d < 16; d <<= 1) {
-      uint32_t y = read_lane(incl, gl >= d ? lane - d : lane);
-      if (gl >= d) incl += y;
+      const uint32_t y = read_lane(incl, cq >= d ? lane - d : lane);
+      if (cq >= d) incl += y;
     }
     const uint32_t off = incl - x;
-    int pos[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const uint32_t base = read_lane(off + pre[s], gbase + (c[s] & 15));
-      pos[s] = st + (int)(base + rank[s]);
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      if (ok[s]) {
-        L.key[pos[s]] = e[s];
-        if constexpr (V) L.val[pos[s]] = v[s];
-      }
-    }
-    // children of this bucket: lane gl describes child gl
-    const bool own = active && gl < nch;
+    const int cst = okq ? (int)L.pend_st[cur][pq] + (int)off : 0;
     const int csz = (int)x;
-    const int cst = st + (int)off;
-    const bool eq = degenerate && gl == 1;
+    const bool eq = dg && cq == 1;
     const bool is_fin = own && !eq && csz >= 2 && csz <= 16;
     const bool is_pend = own && !eq && csz > 16;
     const uint64_t Fm = ballot(is_fin) & gmask;
     const uint64_t Pm = ballot(is_pend) & gmask;
+    if (own) L.cnt[pq][cq] = (uint16_t)off;
     if (is_fin) {
       const int idx = min(nf + (int)__popcll(Fm & below), GroupLds<K, V, G>::kMaxFin - 1);
       L.fin_st[idx] = (uint16_t)cst;
       L.fin_sz[idx] = (uint16_t)csz;
     }
+    int pidx = 0xFF;
     if (is_pend) {
-      const int idx = min(npn + (int)__popcll(Pm & below), GroupLds<K, V, G>::kMaxPend - 1);
-      L.pend_st[cur ^ 1][idx] = (uint16_t)cst;
-      L.pend_sz[cur ^ 1][idx] = (uint16_t)csz;
+      pidx = min(npn + (int)__popcll(Pm & below), GroupLds<K, V, G>::kMaxPend - 1);
+      L.pend_st[cur ^ 1][pidx] = (uint16_t)cst;
+      L.pend_sz[cur ^ 1][pidx] = (uint16_t)csz;
     }
-    nf += (int)__popcll(Fm);
-    npn += (int)__popcll(Pm);
+    if (own) L.nextpb[pq][cq] = (uint8_t)pidx;
     // The list sizes are bounded by the array size (disjoint buckets of at
     // least 2, resp. 17, keys); the clamps only keep every loop bounded.
-    nf = min(nf, GroupLds<K, V, G>::kMaxFin);
-    npn = min(npn, GroupLds<K, V, G>::kMaxPend);
-    wave_lds_sync();
+    nf = min(nf + (int)__popcll(Fm), GroupLds<K, V, G>::kMaxFin);
+    npn = min(npn + (int)__popcll(Pm), GroupLds<K, V, G>::kMaxPend);
   }
+  wave_lds_sync();
+
+  // scatter in place (every key of the slots was read above)
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (ok[s]) {
+      const int pos = (int)L.pend_st[cur][pbk[s]] + (int)L.cnt[pbk[s]][c[s]] + (int)rk[s];
+      L.key[pos] = e[s];
+      if constexpr (V) L.val[pos] = v[s];
+      L.pb[pos] = L.nextpb[pbk[s]][c[s]];
+    }
+  }
+  wave_lds_sync();
 }
 
 // Rank-counting sort of the remaining pending buckets (after kLevelCap levels).
@@ -328,26 +422,24 @@ __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint
       rank_sort_pending(L, cur, np);
       break;
     }
-    // sample + network-sorted sample, one lane per pending bucket
-    if (gl < np) {
-      const int st = L.pend_st[cur][gl];
-      const int sz = L.pend_sz[cur][gl];
-      K smp[16];
-#pragma unroll
-      for (int t = 0; t < 16; ++t) smp[t] = L.key[st + ((2 * t + 1) * sz) / 32];
-      net_sort<F, 16>(smp);
-#pragma unroll
-      for (int t = 0; t < 16; ++t) L.sample[gl][t] = smp[t];
-    }
-    wave_lds_sync();
     const int kk = level == 0 ? k0 : 4;
-    int npn = 0;
-    if (kk == 16)
-      split_level<4>(L, cur, np, nf, npn);
-    else if (kk == 8)
-      split_level<3>(L, cur, np, nf, npn);
+    const int a = oversampling(kk);
+    if (a * kk == 12)
+      sample_phase<F, 12>(L, cur, np, kk, a);
     else
-      split_level<2>(L, cur, np, nf, npn);
+      sample_phase<F, 16>(L, cur, np, kk, a);
+    wave_lds_sync();
+    int npn = 0;
+    if (level == 0) {
+      if (kk == 16)
+        split_level<4, true>(L, m, cur, np, nf, npn);
+      else if (kk == 8)
+        split_level<3, true>(L, m, cur, np, nf, npn);
+      else
+        split_level<2, true>(L, m, cur, np, nf, npn);
+    } else {
+      split_level<2, false>(L, m, cur, np, nf, npn);
+    }
     np = npn;
     cur ^= 1;
   }

@@ -30,6 +30,8 @@
 // rewrites the kernel arguments of its nodes), the same four launched
 // directly, or the "plain" baseline: count/scan/scatter, a copy of the class
 // counts to the host, then one ordinary launch per non-empty class.
+#pragma once
+
 #include <mutex>
 #include <vector>
 
@@ -74,97 +76,14 @@ __host__ __device__ __forceinline__ int class_at(int order) {
   return order < 3 ? 17 - order : 14 - (order - 3);
 }
 
-// --- binning ---------------------------------------------------------------
+// --- binning kernels (segmented_common.hip) -----------------------------------
 
-__global__ void __launch_bounds__(kBinThreads)
-seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg, uint32_t* __restrict__ blockhist,
-                 int* status) {
-  __shared__ uint32_t hist[kClasses];
-  if (threadIdx.x < kClasses) hist[threadIdx.x] = 0;
-  __syncthreads();
-  int bad = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kBinChunk; base < nseg; base += (int64_t)gridDim.x * kBinChunk) {
-#pragma unroll
-    for (int q = 0; q < kBinItems; ++q) {
-      const int64_t i = base + q * kBinThreads + threadIdx.x;
-      if (i < nseg) {
-        const int c = size_class(offsets[i + 1] - offsets[i]);
-        if (c >= 0)
-          atomicAdd(&hist[c], 1u);
-        else if (c < -1)
-          bad = c == -2 ? kStatusTooBig : kStatusInval;
-      }
-    }
-  }
-  if (bad) report(status, bad);
-  __syncthreads();
-  if (threadIdx.x < kClasses) blockhist[threadIdx.x * kBinBlocks + blockIdx.x] = hist[threadIdx.x];
-}
-
-// One block of 1024 threads: class totals, class starts, per-block bases
-// (written over the per-block histogram), tile counter reset.  The histogram
-// is laid out [class][block]; one wave scans one class row of kBinBlocks
-// values, 16 per lane.
-__global__ void __launch_bounds__(1024)
-seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restrict__ ctrl) {
-  constexpr int kPerLane = kBinBlocks / kWave;
-  __shared__ uint32_t tot[kClasses];
-  const int wave = threadIdx.x / kWave;
-  const int lane = lane_id();
-  (void)nblocks;
-  for (int c = wave; c < kClasses; c += 1024 / kWave) {
-    uint32_t* row = blockhist + c * kBinBlocks + lane * kPerLane;
-    uint32_t v[kPerLane];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < kPerLane; ++i) {
-      v[i] = row[i];
-      sum += v[i];
-    }
-    uint32_t incl = sum;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
-      if (lane >= d) incl += y;
-    }
-    uint32_t run = incl - sum;
-#pragma unroll
-    for (int i = 0; i < kPerLane; ++i) {
-      row[i] = run;
-      run += v[i];
-    }
-    if (lane == kWave - 1) tot[c] = incl;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t st = 0;
-    for (int c = 0; c < kClasses; ++c) {
-      ctrl[kCtrlCount + c] = tot[c];
-      ctrl[kCtrlStart + c] = st;
-      st += tot[c];
-    }
-    ctrl[kCtrlTile] = 0;
-  }
-}
-
-__global__ void __launch_bounds__(kBinThreads)
-seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint32_t* __restrict__ blockbase,
-                   const uint32_t* __restrict__ ctrl, int32_t* __restrict__ ids) {
-  __shared__ uint32_t cur[kClasses];
-  if (threadIdx.x < kClasses)
-    cur[threadIdx.x] = ctrl[kCtrlStart + threadIdx.x] + blockbase[threadIdx.x * kBinBlocks + blockIdx.x];
-  __syncthreads();
-  for (int64_t base = (int64_t)blockIdx.x * kBinChunk; base < nseg; base += (int64_t)gridDim.x * kBinChunk) {
-#pragma unroll
-    for (int q = 0; q < kBinItems; ++q) {
-      const int64_t i = base + q * kBinThreads + threadIdx.x;
-      if (i < nseg) {
-        const int c = size_class(offsets[i + 1] - offsets[i]);
-        if (c >= 0) ids[atomicAdd(&cur[c], 1u)] = (int32_t)i;
-      }
-    }
-  }
-}
+__global__ void seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg,
+                                 uint32_t* __restrict__ blockhist, int* status);
+__global__ void seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restrict__ ctrl);
+__global__ void seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg,
+                                   const uint32_t* __restrict__ blockbase, const uint32_t* __restrict__ ctrl,
+                                   int32_t* __restrict__ ids);
 
 // --- tile handlers -----------------------------------------------------------
 
@@ -251,6 +170,7 @@ struct SortArgs {
   const uint32_t* ctrl;
   int rounds;
   int k0[3];
+  int interleave;  // alternate RSS and network tiles in the persistent kernel
 };
 
 // Runs tile `tile_in_class` of class c.
@@ -269,24 +189,69 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint3
   }
 }
 
-// Persistent kernel: waves claim tiles until all are done.
+// Position of tile t in class order: returns the class and the tile index
+// within the class.  The hand-out order lists the RSS classes (most work per
+// tile first) and the network classes; with interleaving, RSS and network
+// tiles alternate while both remain, so memory-bound network tiles overlap
+// with ALU/LDS-bound RSS tiles on every CU.
+__device__ __forceinline__ int class_tiles(const uint32_t* ctrl, int c, int rounds) {
+  const int ts = class_tile(c, rounds);
+  return ((int)ctrl[kCtrlCount + c] + ts - 1) / ts;
+}
+
+__device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rounds, int t_rss, int t_net,
+                                            bool interleave, int& cls, int& idx) {
+  int list_pos;  // position in the concatenated class order
+  if (interleave) {
+    const int both = 2 * min(t_rss, t_net);
+    int i_rss, i_net;  // tile index within the RSS list / network list
+    bool is_rss;
+    if (t < both) {
+      is_rss = (t & 1) == 0;
+      i_rss = i_net = t >> 1;
+    } else {
+      is_rss = t_rss > t_net;
+      i_rss = i_net = t - both + min(t_rss, t_net);
+    }
+    list_pos = is_rss ? i_rss : t_rss + i_net;
+  } else {
+    list_pos = t;
+  }
+  // walk the classes in hand-out order (wave-uniform scalar loads)
+  cls = class_at(kClasses - 1);
+  idx = 0;
+  int acc = 0;
+  for (int o = 0; o < kClasses; ++o) {
+    const int c = class_at(o);
+    const int n = class_tiles(ctrl, c, rounds);
+    if (list_pos < acc + n) {
+      cls = c;
+      idx = list_pos - acc;
+      break;
+    }
+    acc += n;
+  }
+}
+
+// Persistent kernel: waves claim tiles (chunk at a time, one atomic) until all
+// are done.  Limited to the registers of three waves per SIMD so that the
+// latency-bound RSS tiles keep enough waves in flight.
 template <int F, class K, bool V>
-__global__ void __launch_bounds__(kSortThreads)
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(3)))
 seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip,
                       int chunk) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][WaveLds<K, V>::kBytes];
   const int wave = threadIdx.x / kWave;
-  // tile prefix over classes in hand-out order (wave-uniform values)
-  int ntiles[kClasses];
-  int total = 0;
-#pragma unroll
-  for (int o = 0; o < kClasses; ++o) {
-    const int c = class_at(o);
-    const int cnt = (int)a.ctrl[kCtrlCount + c];
-    const int ts = class_tile(c, a.rounds);
-    ntiles[o] = (cnt + ts - 1) / ts;
-    total += ntiles[o];
+  // tiles of the RSS classes and of the network classes (wave-uniform)
+  int t_rss = 0, t_net = 0;
+  for (int c = 0; c < kClasses; ++c) {
+    const int n = class_tiles(a.ctrl, c, a.rounds);
+    if (c >= kNetClasses)
+      t_rss += n;
+    else
+      t_net += n;
   }
+  const int total = t_rss + t_net;
   while (true) {
     int t0 = 0;
     if (lane_id() == 0) t0 = (int)atomicAdd(&ctrl[kCtrlTile], (uint32_t)chunk);
@@ -294,30 +259,35 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
     if (t0 >= total) break;
     const int t1 = min(t0 + chunk, total);
     for (int t = t0; t < t1; ++t) {
-      int c = 0, base = 0, acc = 0;
-#pragma unroll
-      for (int o = 0; o < kClasses; ++o) {
-        if (t >= acc && t < acc + ntiles[o]) {
-          c = class_at(o);
-          base = acc;
-        }
-        acc += ntiles[o];
-      }
-      run_tile<F, K, V>(lds[wave], keys, vals, a, flip, c, t - base, (int)a.ctrl[kCtrlCount + c],
+      int c, idx;
+      locate_tile(t, a.ctrl, a.rounds, t_rss, t_net, a.interleave != 0, c, idx);
+      run_tile<F, K, V>(lds[wave], keys, vals, a, flip, c, idx, (int)a.ctrl[kCtrlCount + c],
                         (int)a.ctrl[kCtrlStart + c]);
     }
   }
 }
 
-// Plain baseline: one launch per class, tile = blockIdx * waves + wave.
-template <int F, class K, bool V>
+// Plain baseline: one launch per class, tile = blockIdx * waves + wave.  The
+// kernel is specialised per handler (KIND 0: networks, 1..3: RSS with 16-,
+// 32-, 64-lane groups), so each launch carries only its own code and
+// registers.
+template <int F, class K, bool V, int KIND>
 __global__ void __launch_bounds__(kSortThreads)
 seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, K flip, int c, int count,
                  int list) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][WaveLds<K, V>::kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][KIND == 0 ? 16 : WaveLds<K, V>::kBytes];
   const int wave = threadIdx.x / kWave;
   const int tile = blockIdx.x * kSortWaves + wave;
-  run_tile<F, K, V>(lds[wave], keys, vals, a, flip, c, tile, count, list);
+  const int first = tile * class_tile(c, a.rounds);
+  if constexpr (KIND == 0) {
+    net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
+  } else if constexpr (KIND == 1) {
+    rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[0]);
+  } else if constexpr (KIND == 2) {
+    rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[1]);
+  } else {
+    rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[2]);
+  }
 }
 
 // --- host side ---------------------------------------------------------------
@@ -341,30 +311,7 @@ struct SegmentedCache {
   std::vector<GraphEntry> graphs;
 };
 
-static hipError_t ensure_workspace(DeviceCtx* c, int32_t nseg) {
-  SegmentedCache* s = c->seg;
-  hipError_t e = hipSuccess;
-  if (!s->ctrl) {
-    e = hipMalloc(&s->ctrl, kCtrlWords * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&s->blockhist, kBinBlocks * kClasses * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc(&s->host_ctrl, kCtrlWords * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
-  }
-  if (s->ids_cap < nseg) {
-    // growing: wait for in-flight users of the old list before freeing it
-    e = hipDeviceSynchronize();
-    if (e == hipSuccess && s->ids) e = hipFree(s->ids);
-    s->ids = nullptr;
-    s->ids_cap = 0;
-    int64_t cap = nseg < 1024 ? 1024 : (int64_t)nseg + nseg / 4;
-    if (cap > 0x7FFFFFFF) cap = 0x7FFFFFFF;
-    if (e == hipSuccess) e = hipMalloc(&s->ids, cap * sizeof(int32_t));
-    if (e != hipSuccess) return e;
-    s->ids_cap = cap;
-  }
-  return hipSuccess;
-}
+hipError_t ensure_workspace(DeviceCtx* c, int32_t nseg);
 
 template <int F, class K, bool V>
 static int persistent_blocks(DeviceCtx* c) {
@@ -380,7 +327,7 @@ static int persistent_blocks(DeviceCtx* c) {
   return occ * c->num_cus;
 }
 
-static SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
+inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
   SortArgs a;
   a.offsets = offsets;
   a.ids = s->ids;
@@ -389,6 +336,7 @@ static SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
   a.k0[0] = tuning().rss_k[0];
   a.k0[1] = tuning().rss_k[1];
   a.k0[2] = tuning().rss_k[2];
+  a.interleave = tuning().interleave;
   return a;
 }
 
@@ -505,8 +453,19 @@ static hipError_t run_plain(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) 
     const int ts = class_tile(cls, L.args.rounds);
     const int tiles = (count + ts - 1) / ts;
     const int blocks = (tiles + kSortWaves - 1) / kSortWaves;
-    hipLaunchKernelGGL((seg_class_kernel<F, K, V>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
-                       L.args, L.flip, cls, count, (int)sc->host_ctrl[kCtrlStart + cls]);
+    const int list = (int)sc->host_ctrl[kCtrlStart + cls];
+    if (cls < kNetClasses)
+      hipLaunchKernelGGL((seg_class_kernel<F, K, V, 0>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
+                         L.args, L.flip, cls, count, list);
+    else if (cls == 15)
+      hipLaunchKernelGGL((seg_class_kernel<F, K, V, 1>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
+                         L.args, L.flip, cls, count, list);
+    else if (cls == 16)
+      hipLaunchKernelGGL((seg_class_kernel<F, K, V, 2>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
+                         L.args, L.flip, cls, count, list);
+    else
+      hipLaunchKernelGGL((seg_class_kernel<F, K, V, 3>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
+                         L.args, L.flip, cls, count, list);
   }
   return hipGetLastError();
 }
@@ -581,15 +540,6 @@ static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* o
     return fam ? segmented_impl<1, K, false>(c, keys, vals, offsets, nseg, flip, mode, s)
                : segmented_impl<0, K, false>(c, keys, vals, offsets, nseg, flip, mode, s);
   }
-}
-
-int segmented_u32(DeviceCtx* c, uint32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
-                  uint32_t flip, int mode, hipStream_t s) {
-  return segmented_any<uint32_t>(c, keys, vals, offsets, nseg, flip, mode, s);
-}
-int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
-                  uint64_t flip, int mode, hipStream_t s) {
-  return segmented_any<uint64_t>(c, keys, vals, offsets, nseg, flip, mode, s);
 }
 
 }  // namespace ss

@@ -1,0 +1,121 @@
+// Binning kernels and working memory of the segmented path (see segmented.hpp).
+#include "segmented.hpp"
+
+namespace ss {
+
+__global__ void __launch_bounds__(kBinThreads)
+seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg, uint32_t* __restrict__ blockhist,
+                 int* status) {
+  __shared__ uint32_t hist[kClasses];
+  if (threadIdx.x < kClasses) hist[threadIdx.x] = 0;
+  __syncthreads();
+  int bad = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBinChunk; base < nseg; base += (int64_t)gridDim.x * kBinChunk) {
+#pragma unroll
+    for (int q = 0; q < kBinItems; ++q) {
+      const int64_t i = base + q * kBinThreads + threadIdx.x;
+      if (i < nseg) {
+        const int c = size_class(offsets[i + 1] - offsets[i]);
+        if (c >= 0)
+          atomicAdd(&hist[c], 1u);
+        else if (c < -1)
+          bad = c == -2 ? kStatusTooBig : kStatusInval;
+      }
+    }
+  }
+  if (bad) report(status, bad);
+  __syncthreads();
+  if (threadIdx.x < kClasses) blockhist[threadIdx.x * kBinBlocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+// One block of 1024 threads: class totals, class starts, per-block bases
+// (written over the per-block histogram), tile counter reset.  The histogram
+// is laid out [class][block]; one wave scans one class row of kBinBlocks
+// values, 16 per lane.
+__global__ void __launch_bounds__(1024)
+seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restrict__ ctrl) {
+  constexpr int kPerLane = kBinBlocks / kWave;
+  __shared__ uint32_t tot[kClasses];
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  (void)nblocks;
+  for (int c = wave; c < kClasses; c += 1024 / kWave) {
+    uint32_t* row = blockhist + c * kBinBlocks + lane * kPerLane;
+    uint32_t v[kPerLane];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+      v[i] = row[i];
+      sum += v[i];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, d);
+      if (lane >= d) incl += y;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+      row[i] = run;
+      run += v[i];
+    }
+    if (lane == kWave - 1) tot[c] = incl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t st = 0;
+    for (int c = 0; c < kClasses; ++c) {
+      ctrl[kCtrlCount + c] = tot[c];
+      ctrl[kCtrlStart + c] = st;
+      st += tot[c];
+    }
+    ctrl[kCtrlTile] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBinThreads)
+seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint32_t* __restrict__ blockbase,
+                   const uint32_t* __restrict__ ctrl, int32_t* __restrict__ ids) {
+  __shared__ uint32_t cur[kClasses];
+  if (threadIdx.x < kClasses)
+    cur[threadIdx.x] = ctrl[kCtrlStart + threadIdx.x] + blockbase[threadIdx.x * kBinBlocks + blockIdx.x];
+  __syncthreads();
+  for (int64_t base = (int64_t)blockIdx.x * kBinChunk; base < nseg; base += (int64_t)gridDim.x * kBinChunk) {
+#pragma unroll
+    for (int q = 0; q < kBinItems; ++q) {
+      const int64_t i = base + q * kBinThreads + threadIdx.x;
+      if (i < nseg) {
+        const int c = size_class(offsets[i + 1] - offsets[i]);
+        if (c >= 0) ids[atomicAdd(&cur[c], 1u)] = (int32_t)i;
+      }
+    }
+  }
+}
+
+hipError_t ensure_workspace(DeviceCtx* c, int32_t nseg) {
+  SegmentedCache* s = c->seg;
+  hipError_t e = hipSuccess;
+  if (!s->ctrl) {
+    e = hipMalloc(&s->ctrl, kCtrlWords * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&s->blockhist, kBinBlocks * kClasses * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipHostMalloc(&s->host_ctrl, kCtrlWords * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  if (s->ids_cap < nseg) {
+    // growing: wait for in-flight users of the old list before freeing it
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess && s->ids) e = hipFree(s->ids);
+    s->ids = nullptr;
+    s->ids_cap = 0;
+    int64_t cap = nseg < 1024 ? 1024 : (int64_t)nseg + nseg / 4;
+    if (cap > 0x7FFFFFFF) cap = 0x7FFFFFFF;
+    if (e == hipSuccess) e = hipMalloc(&s->ids, cap * sizeof(int32_t));
+    if (e != hipSuccess) return e;
+    s->ids_cap = cap;
+  }
+  return hipSuccess;
+}
+
+}  // namespace ss

@@ -1,0 +1,11 @@
+// Segmented sort entry for uint64_t keys (kernels instantiated here; see segmented.hpp).
+#include "segmented.hpp"
+
+namespace ss {
+
+int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, uint64_t flip,
+                  int mode, hipStream_t s) {
+  return segmented_any<uint64_t>(c, keys, vals, offsets, nseg, flip, mode, s);
+}
+
+}  // namespace ss
