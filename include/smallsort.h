@@ -27,12 +27,13 @@
  *     Errors that depend on device data (a segment longer than 256 keys, a
  *     decreasing offset) are recorded in a per-device status word, read with
  *     ss_device_status; the affected segment is left unsorted.
- *   - Working memory (counters, size-class lists, graph cache) is allocated
- *     once per device on first use and grown when a larger batch arrives;
- *     calls of the same or smaller shape allocate nothing.
- *   - Calls are thread-safe; calls that overlap on one device share its
- *     working memory, so concurrent segmented sorts must use one stream or be
- *     externally ordered.
+ *   - Working memory of the segmented path (counters, size-class lists,
+ *     cached graph) is allocated per (device, stream) on first use and grown
+ *     (after a device synchronisation) when a larger batch arrives; calls of
+ *     the same or smaller shape allocate nothing.
+ *   - Calls are thread-safe.  Segmented sorts on different streams use
+ *     separate working memory and may overlap on the device; calls on one
+ *     stream are ordered by that stream.
  */
 #ifndef SMALLSORT_H
 #define SMALLSORT_H
@@ -123,12 +124,16 @@ const char *ss_strerror(ss_status status);
 
 /*
  * Tuning parameters (variant choices found by the autotuner).  Names:
- *   "family"         network family for n <= 16: 0 = fewest comparators, 1 = Bose-Nelson
- *   "rss_k_small"    splitters+1 (4, 8 or 16) for buckets of 17..64 keys
- *   "rss_k_mid"      same for 65..128 keys
- *   "rss_k_large"    same for 129..256 keys
- *   "tile_chunk"     tiles claimed per atomic by the persistent kernel (1..64)
- *   "persist_occ"    resident work-groups per CU for the persistent grid (1..16)
+ *   "family"       network family: 0 = fewest comparators, 1 = Bose-Nelson
+ *   "rss_k_small"  buckets (4, 8 or 16; splitters + 1) of the first Register
+ *                  Sample Sort level for arrays of 17..64 keys
+ *   "rss_k_mid"    same for arrays of 65..128 keys
+ *   "rss_k_large"  same for arrays of 129..256 keys
+ *   "tile_chunk"   tiles claimed per atomic by the persistent kernel (1..64)
+ *   "persist_occ"  work-groups per CU of the persistent grid (0 = as many as
+ *                  fit, 1..16)
+ *   "rss_rounds"   rounds of lane groups per RSS tile in segmented sorts (1..16)
+ *   "interleave"   1: the persistent kernel alternates RSS and network tiles
  * ss_set_tuning_value returns SS_ENOTUNE for an unknown name, SS_EINVAL for a
  * value out of range.  ss_get_tuning_value returns -1 for an unknown name.
  * ss_load_tuning reads a flat JSON object {"name": integer, ...} with these

@@ -16,7 +16,7 @@ import threading
 
 __all__ = [
     "SmallSortError", "lib", "lib_path", "sort_small", "segmented_sort", "device_status",
-    "set_tuning", "get_tuning", "load_tuning", "version", "KEY_CODES",
+    "set_tuning", "get_tuning", "load_tuning", "tuning_path", "version", "KEY_CODES",
     "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN",
 ]
 
@@ -76,7 +76,33 @@ def lib() -> ctypes.CDLL:
                 f.restype = res
                 f.argtypes = args
             _lib = handle
+            _autoload_tuning(handle)
     return _lib
+
+
+def tuning_path() -> str:
+    return os.environ.get("SMALLSORT_TUNING", os.path.join(_HERE, "tuning_gfx950.json"))
+
+
+def _autoload_tuning(handle):
+    """Apply the autotuner's saved choices if they were measured on this ROCm.
+
+    SMALLSORT_TUNING=<path> selects another file, SMALLSORT_TUNING=none
+    disables loading.  A file recorded under another ROCm version is ignored
+    (the defaults apply until the tuner is run again).
+    """
+    import json
+    path = tuning_path()
+    if path == "none" or not os.path.exists(path):
+        return
+    try:
+        doc = json.load(open(path))
+        import torch
+        if doc.get("rocm") not in (None, str(torch.version.hip)):
+            return
+    except (OSError, ValueError, ImportError):
+        return
+    handle.ss_load_tuning(os.fsencode(path))
 
 
 def _check(status, what):

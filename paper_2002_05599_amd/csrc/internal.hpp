@@ -31,12 +31,12 @@ hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t st
 
 // Per-device context: status word, device properties and working memory
 // for the segmented path (grown on demand, freed at process exit).
-struct SegmentedCache;  // defined with the segmented kernels
+struct SegRegistry;  // per-stream working memory of the segmented path
 struct DeviceCtx {
   int device = -1;
   int num_cus = 0;
-  int* status = nullptr;          // device int32 status word
-  SegmentedCache* seg = nullptr;  // working memory + graphs of the segmented path
+  int* status = nullptr;       // device int32 status word
+  SegRegistry* seg = nullptr;  // segmented-path workspaces, one per stream
 };
 // Context of the current device, created on first use; nullptr on failure
 // with *err set to a HIP error.

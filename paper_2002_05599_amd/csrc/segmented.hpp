@@ -307,11 +307,14 @@ struct SegmentedCache {
   uint32_t* ctrl = nullptr;
   uint32_t* blockhist = nullptr;
   uint32_t* host_ctrl = nullptr;  // pinned, for the plain baseline
-  hipStream_t capture_stream = nullptr;
   std::vector<GraphEntry> graphs;
 };
 
-hipError_t ensure_workspace(DeviceCtx* c, int32_t nseg);
+// Working memory of the stream `s` on this device (created on first use; calls
+// on different streams never share it, so they may overlap on the device).
+SegmentedCache* workspace_for(DeviceCtx* c, hipStream_t s);
+// Grows the workspace's segment-id list to hold nseg ids (caller holds ws->mu).
+hipError_t ensure_workspace(SegmentedCache* ws, int32_t nseg);
 
 template <int F, class K, bool V>
 static int persistent_blocks(DeviceCtx* c) {
@@ -364,8 +367,7 @@ struct SegLaunch {
   void* p_sort[6];
   int persist_blocks;
 
-  void fill(DeviceCtx* c, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
-    SegmentedCache* s = c->seg;
+  void fill(DeviceCtx* c, SegmentedCache* s, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
     offsets = off;
     nseg = n;
     blockhist = s->blockhist;
@@ -439,8 +441,7 @@ struct SegLaunch {
 };
 
 template <int F, class K, bool V>
-static hipError_t run_plain(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) {
-  SegmentedCache* sc = c->seg;
+static hipError_t run_plain(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
   hipError_t e = L.launch_binning(s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, kCtrlWords * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -471,8 +472,7 @@ static hipError_t run_plain(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) 
 }
 
 template <int F, class K, bool V>
-static hipError_t run_graph(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) {
-  SegmentedCache* sc = c->seg;
+static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
   const int key = (int)sizeof(K) * 4 + (V ? 2 : 0) + F;
   GraphEntry* g = nullptr;
   for (GraphEntry& ge : sc->graphs)
@@ -505,18 +505,18 @@ static hipError_t run_graph(DeviceCtx* c, SegLaunch<F, K, V>& L, hipStream_t s) 
 }
 
 template <int F, class K, bool V>
-static int segmented_impl(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, K flip,
-                          int mode, hipStream_t s) {
+static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets,
+                          int32_t nseg, K flip, int mode, hipStream_t s) {
   SegLaunch<F, K, V> L;
   L.persist_blocks = persistent_blocks<F, K, V>(c);
-  L.fill(c, keys, vals, offsets, nseg, flip);
+  L.fill(c, ws, keys, vals, offsets, nseg, flip);
   hipError_t e;
   if (mode == 2)
-    e = run_plain(c, L, s);
+    e = run_plain(ws, L, s);
   else if (mode == 1)
     e = L.launch_direct(s);
   else
-    e = run_graph(c, L, s);
+    e = run_graph(ws, L, s);
   if (e == hipErrorOutOfMemory) return -5;
   return e == hipSuccess ? 0 : -4;
 }
@@ -524,22 +524,17 @@ static int segmented_impl(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* 
 template <class K>
 static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, K flip,
                          int mode, hipStream_t s) {
-  {
-    {
-      static std::mutex create_mu;
-      std::lock_guard<std::mutex> lock(create_mu);
-      if (!c->seg) c->seg = new SegmentedCache();
-    }
-    std::lock_guard<std::mutex> lock(c->seg->mu);
-    hipError_t e = ensure_workspace(c, nseg);
-    if (e != hipSuccess) return e == hipErrorOutOfMemory ? -5 : -4;
-    const bool fam = tuning().family == 1;
-    if (vals)
-      return fam ? segmented_impl<1, K, true>(c, keys, vals, offsets, nseg, flip, mode, s)
-                 : segmented_impl<0, K, true>(c, keys, vals, offsets, nseg, flip, mode, s);
-    return fam ? segmented_impl<1, K, false>(c, keys, vals, offsets, nseg, flip, mode, s)
-               : segmented_impl<0, K, false>(c, keys, vals, offsets, nseg, flip, mode, s);
-  }
+  SegmentedCache* ws = workspace_for(c, s);
+  if (!ws) return -5;
+  std::lock_guard<std::mutex> lock(ws->mu);
+  hipError_t e = ensure_workspace(ws, nseg);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? -5 : -4;
+  const bool fam = tuning().family == 1;
+  if (vals)
+    return fam ? segmented_impl<1, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
+               : segmented_impl<0, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
+  return fam ? segmented_impl<1, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
+             : segmented_impl<0, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
 }
 
 }  // namespace ss

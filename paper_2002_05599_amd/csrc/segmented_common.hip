@@ -93,16 +93,37 @@ seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint
   }
 }
 
-hipError_t ensure_workspace(DeviceCtx* c, int32_t nseg) {
-  SegmentedCache* s = c->seg;
-  hipError_t e = hipSuccess;
-  if (!s->ctrl) {
-    e = hipMalloc(&s->ctrl, kCtrlWords * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&s->blockhist, kBinBlocks * kClasses * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipHostMalloc(&s->host_ctrl, kCtrlWords * sizeof(uint32_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return e;
+struct SegRegistry {
+  std::mutex mu;
+  std::vector<std::pair<hipStream_t, SegmentedCache*>> list;
+};
+
+SegmentedCache* workspace_for(DeviceCtx* c, hipStream_t s) {
+  static std::mutex create_mu;
+  {
+    std::lock_guard<std::mutex> lock(create_mu);
+    if (!c->seg) c->seg = new SegRegistry();
   }
+  SegRegistry* r = c->seg;
+  std::lock_guard<std::mutex> lock(r->mu);
+  for (auto& e : r->list)
+    if (e.first == s) return e.second;
+  SegmentedCache* ws = new SegmentedCache();
+  hipError_t e = hipMalloc(&ws->ctrl, kCtrlWords * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&ws->blockhist, kBinBlocks * kClasses * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipHostMalloc(&ws->host_ctrl, kCtrlWords * sizeof(uint32_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (ws->ctrl) (void)hipFree(ws->ctrl);
+    if (ws->blockhist) (void)hipFree(ws->blockhist);
+    delete ws;
+    return nullptr;
+  }
+  r->list.emplace_back(s, ws);
+  return ws;
+}
+
+hipError_t ensure_workspace(SegmentedCache* s, int32_t nseg) {
+  hipError_t e = hipSuccess;
   if (s->ids_cap < nseg) {
     // growing: wait for in-flight users of the old list before freeing it
     e = hipDeviceSynchronize();
