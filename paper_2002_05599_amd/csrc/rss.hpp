@@ -17,9 +17,9 @@
 //      (the paper's "unconditional copy of the left subtree, conditionally
 //      overwritten with the right one"), and append the comparison bit to the
 //      bucket index, j = 2j + [e > root];
-//   4. scatter: a stable multisplit -- per-slot ballots of the bucket-index
-//      bits give each key its rank among equal buckets, per-bucket counts are
-//      scanned into offsets -- and the keys are written back in bucket order;
+//   4. scatter: a multisplit -- LDS atomic counters give each key its rank
+//      within its bucket, per-bucket counts are scanned into offsets -- and
+//      the keys are written back in bucket order;
 //   5. buckets of 2..16 keys join the finish list, larger ones are pending
 //      for the next level (the paper recurses until buckets are at most 16).
 //
@@ -52,7 +52,7 @@ template <class K, bool V, int G> struct GroupLds {
   K key[kCap];
   uint32_t val[V ? kCap : 1];
   K sample[kMaxPend][16];          // sorted sample of each pending bucket
-  uint16_t cnt[kMaxPend][16];      // per (bucket, child): count, then child offset
+  uint32_t cnt[kMaxPend][16];      // per (bucket, child): count, then child offset
   uint8_t nextpb[kMaxPend][16];    // pending index of each child at the next level, or 0xFF
   uint8_t deg[kMaxPend];           // all splitters of the bucket equal
   uint8_t pb[kCap];                // pending bucket of each position, or 0xFF
@@ -203,15 +203,13 @@ __device__ __forceinline__ int three_way(K e, K v) {
 // levels take each key's bucket from pb[] and search that bucket's sample in
 // LDS.
 //
-// Stable multisplit: in slot s the lanes hold positions gl + G*s, so the keys
-// of one pending bucket occupy a contiguous lane range.  A key's rank among
-// the keys with the same (bucket, child) is the running count cnt[b][c] plus
-// the number of lower lanes in the same range whose child index matches
-// (ballots of the child-index bits); the lowest such lane then advances
-// cnt[b][c].  Per bucket, the counts are scanned into child offsets, the
-// children are registered (finish list or next-level pending list, in
-// position order) and every key is written to bucket start + child offset +
-// rank, together with its next-level bucket id.
+// Multisplit: each key takes its rank among the keys of the same (bucket,
+// child) from an LDS atomic counter cnt[b][c] (one ds_add_rtn per key; the
+// order of equal-child keys inside a bucket does not matter, because every
+// bucket is sorted afterwards).  Per bucket, the counts are scanned into child
+// offsets, the children are registered (finish list or next-level pending
+// list, in position order) and every key is written to bucket start + child
+// offset + rank, together with its next-level bucket id.
 template <int LOGK, bool kFirst, class K, bool V, int G>
 __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
   constexpr int k = 1 << LOGK;
@@ -250,38 +248,22 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     e[s] = ok[s] ? L.key[i] : K(0);
     if constexpr (V) v[s] = ok[s] ? L.val[i] : 0u;
     int cc;
-    uint64_t same_b;
     if constexpr (kFirst) {
-      cc = deg0 ? three_way(e[s], spl[0]) : classify<LOGK>(e[s], spl);
-      same_b = gmask;
+      cc = classify<LOGK>(e[s], spl);
+      if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], spl[0]);
     } else {
       const int q = ok[s] ? pp : 0;
       const K* smp = L.sample[q];
+      cc = lds_bucket<LOGK, a>(e[s], smp);
       const bool dg = L.deg[q] != 0;
-      cc = dg ? three_way(e[s], smp[a - 1]) : lds_bucket<LOGK, a>(e[s], smp);
-      // lanes of this slot inside the bucket's position range
-      const int st = L.pend_st[cur][q];
-      const int sz = L.pend_sz[cur][q];
-      const int lo = min(max(st - G * s, 0), G);
-      const int hi = min(max(st + sz - G * s, 0), G);
-      const uint64_t hm = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
-      const uint64_t lm = (1ull << lo) - 1ull;
-      same_b = (hm & ~lm) << gbase;
+      if (ballot(dg) != 0ull && dg) cc = three_way(e[s], smp[a - 1]);
     }
     c[s] = cc;
     pbk[s] = pp;
-    uint64_t my = ballot(ok[s]) & gmask & same_b;
-#pragma unroll
-    for (int b = 0; b < LOGK; ++b) {
-      const uint64_t B = ballot(ok[s] && ((cc >> b) & 1));
-      my &= ((cc >> b) & 1) ? B : ~B;
-    }
-    const uint32_t r = (uint32_t)__popcll(my & below);
-    const uint32_t base = ok[s] ? (uint32_t)L.cnt[ok[s] ? pp : 0][cc] : 0u;
-    rk[s] = base + r;
-    if (ok[s] && r == 0) L.cnt[pp][cc] = (uint16_t)(base + (uint32_t)__popcll(my));
-    wave_lds_sync();
+    // rank among the keys of the same (bucket, child): an LDS atomic counter
+    rk[s] = ok[s] ? atomicAdd(&L.cnt[pp][cc], 1u) : 0u;
   }
+  wave_lds_sync();
 
   // scan each bucket's child counts into offsets; register the children
   for (int r0 = 0; ballot(r0 < np * 16) != 0ull; r0 += G) {
@@ -292,7 +274,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     const bool dg = okq && L.deg[pq] != 0;
     const int nchq = okq ? (dg ? 3 : k) : 0;
     const bool own = cq < nchq;
-    const uint32_t x = own ? (uint32_t)L.cnt[pq][cq] : 0u;
+    const uint32_t x = own ? L.cnt[pq][cq] : 0u;
     uint32_t incl = x;
 #pragma unroll
     for (int d = 1; d < 16; d <<= 1) {
@@ -307,7 +289,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     const bool is_pend = own && !eq && csz > 16;
     const uint64_t Fm = ballot(is_fin) & gmask;
     const uint64_t Pm = ballot(is_pend) & gmask;
-    if (own) L.cnt[pq][cq] = (uint16_t)off;
+    if (own) L.cnt[pq][cq] = off;
     if (is_fin) {
       const int idx = min(nf + (int)__popcll(Fm & below), GroupLds<K, V, G>::kMaxFin - 1);
       L.fin_st[idx] = (uint16_t)cst;
