@@ -220,13 +220,18 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
   const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
   const uint64_t below = (1ull << lane) - 1ull;
 
-  // level 0: splitters s_1..s_{k-1} in registers (paper, Section 3)
-  K spl[k - 1];
+  // Level 0 with few, narrow splitters: s_1..s_{k-1} held in registers and
+  // searched by the register tree (paper, Section 3).  Wider trees would take
+  // more VGPRs than they save and cost occupancy, so they are searched in LDS.
+  constexpr bool kRegTree = kFirst && (k - 1) * (int)sizeof(K) <= 32;
+  K spl[kRegTree ? k - 1 : 1];
   bool deg0 = false;
-  if constexpr (kFirst) {
+  if constexpr (kRegTree) {
 #pragma unroll
     for (int i = 0; i < k - 1; ++i) spl[i] = np > 0 ? L.sample[0][a * (i + 1) - 1] : K(0);
     deg0 = np > 0 && spl[0] == spl[k - 2];
+  } else if constexpr (kFirst) {
+    deg0 = np > 0 && L.deg[0] != 0;
   }
 
   K e[4];
@@ -248,9 +253,13 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     e[s] = ok[s] ? L.key[i] : K(0);
     if constexpr (V) v[s] = ok[s] ? L.val[i] : 0u;
     int cc;
-    if constexpr (kFirst) {
+    if constexpr (kRegTree) {
       cc = classify<LOGK>(e[s], spl);
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], spl[0]);
+    } else if constexpr (kFirst) {
+      const K* smp = L.sample[0];
+      cc = lds_bucket<LOGK, a>(e[s], smp);
+      if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], smp[a - 1]);
     } else {
       const int q = ok[s] ? pp : 0;
       const K* smp = L.sample[q];
