@@ -233,11 +233,18 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
   }
 }
 
+// Waves per SIMD the persistent kernel is compiled for: its register budget.
+// It holds every handler, so unconstrained it would take more registers than
+// the largest of them and lose occupancy, which the latency-bound RSS tiles
+// need.
+template <class K, bool V> struct PersistWaves {
+  static constexpr int value = sizeof(K) == 4 ? (V ? 4 : 5) : (V ? 3 : 4);
+};
+
 // Persistent kernel: waves claim tiles (chunk at a time, one atomic) until all
-// are done.  Limited to the registers of three waves per SIMD so that the
-// latency-bound RSS tiles keep enough waves in flight.
+// are done.
 template <int F, class K, bool V>
-__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(PersistWaves<K, V>::value)))
 seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip,
                       int chunk) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][WaveLds<K, V>::kBytes];
