@@ -157,6 +157,20 @@ def tune(quick=False, reps=5, log=print):
     return best, report
 
 
+def compare_modes(reps=5):
+    """Graph vs plain on the RSS-only batch (all three RSS classes) and the ragged batch."""
+    import torch
+    from . import inputs, segmented_sort, MODE_AUTO, MODE_PLAIN
+    off = inputs.offsets_from_sizes(inputs.csr_sizes(1 << 19, 17, 256, seed=7))
+    k = torch.from_numpy(inputs.random_keys(np.int32, int(off[-1]), seed=7)).cuda()
+    src = k.clone()
+    to = torch.from_numpy(off).cuda()
+    out = {}
+    for name, mode in (("graph", MODE_AUTO), ("plain", MODE_PLAIN)):
+        out[f"rss_{name}_ms"] = _timer(lambda: segmented_sort(k, to, mode=mode), lambda: k.copy_(src), reps)
+    return out
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--quick", action="store_true", help="smaller workloads")
@@ -169,6 +183,8 @@ def main():
     arch, rocm = system_tag()
     t0 = time.time()
     best, report = tune(quick=args.quick, reps=args.reps, log=lambda s: print(s, flush=True))
+    report.update(compare_modes(args.reps))
+    print(json.dumps({k: v for k, v in report.items() if k.endswith("_ms")}), flush=True)
     out = args.out or default_path(arch)
     doc = dict(best)
     doc.update({"arch": arch, "rocm": rocm})
