@@ -134,6 +134,9 @@ const char *ss_strerror(ss_status status);
  *                  fit, 1..16)
  *   "rss_rounds"   rounds of lane groups per RSS tile in segmented sorts (1..16)
  *   "interleave"   1: the persistent kernel alternates RSS and network tiles
+ *   "persist_split" 1: a persistent kernel for the network classes, then one
+ *                  per RSS size class (each with only its own code and
+ *                  registers); 0: a single persistent kernel for every class
  * ss_set_tuning_value returns SS_ENOTUNE for an unknown name, SS_EINVAL for a
  * value out of range.  ss_get_tuning_value returns -1 for an unknown name.
  * ss_load_tuning reads a flat JSON object {"name": integer, ...} with these

@@ -121,6 +121,7 @@ SPACE = [
     ("rss_k_large", [4, 8, 16], "rss"),
     ("rss_rounds", [2, 4, 8, 16], "ragged"),
     ("tile_chunk", [1, 2, 4, 8, 16], "ragged"),
+    ("persist_split", [0, 1], "ragged"),
     ("interleave", [0, 1], "ragged"),
     ("persist_occ", [0, 1, 2, 3], "ragged"),
 ]

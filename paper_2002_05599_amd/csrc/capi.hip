@@ -138,6 +138,7 @@ static std::vector<TuneEntry> tune_table() {
       {"persist_occ", &t.persist_occ, 0, 16, false},
       {"rss_rounds", &t.rss_rounds, 1, 16, false},
       {"interleave", &t.interleave, 0, 1, false},
+      {"persist_split", &t.persist_split, 0, 1, false},
   };
 }
 

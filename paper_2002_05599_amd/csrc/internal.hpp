@@ -14,6 +14,7 @@ struct Tuning {
   int persist_occ = 0;   // work-groups per CU for the persistent grid (0 = occupancy limit)
   int rss_rounds = 8;    // rounds of groups per RSS tile in the segmented kernels
   int interleave = 1;    // persistent kernel alternates RSS and network tiles
+  int persist_split = 1;  // 1: one persistent kernel per kind (networks, each RSS class); 0: one for all
 };
 Tuning& tuning();
 

@@ -150,30 +150,48 @@ __device__ __forceinline__ void finish_dispatch(GroupLds<K, V, G>& L, bool ok, i
 // parameters the paper found best on most machines ("332", Section 4.5).
 __host__ __device__ constexpr int oversampling(int k) { return k == 4 ? 3 : 16 / k; }
 
-// Sample of NS = a*k keys at positions floor((2t+1)*size/(2*NS)) of each
-// pending bucket (one lane per bucket), sorted by the NS-channel network;
-// also clears the bucket's child counters and records whether all of its
-// k-1 splitters are equal.
-template <int F, int NS, class K, bool V, int G>
-__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np, int k, int a) {
-  const int gl = lane_id() % G;
-  if (gl < np) {
-    const int st = L.pend_st[cur][gl];
-    const int sz = L.pend_sz[cur][gl];
-    K smp[NS];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) smp[t] = L.key[st + ((2 * t + 1) * sz) / (2 * NS)];
-    net_sort<F, NS>(smp);
-    K lo_s = smp[0], hi_s = smp[0];
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      L.sample[gl][t] = smp[t];
-      if (t == a - 1) lo_s = smp[t];
-      if (t == a * (k - 1) - 1) hi_s = smp[t];
+// Sample of NS = a*k keys (k = KB buckets) at positions
+// floor((2t+1)*size/(2*NS)) of each pending bucket (one lane per bucket),
+// sorted by the NS-channel network; also clears the bucket's child counters
+// and records whether all of its k-1 splitters are equal.
+template <int F, int KB, class K, bool V, int G>
+__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
+  constexpr int A = oversampling(KB);
+  constexpr int NS = A * KB;
+  constexpr int PER = G / NS;  // buckets sampled per pass (one NS-lane team each)
+  const int lane = lane_id();
+  const int gl = lane % G;
+  const int team = gl / NS;
+  const int t = gl - team * NS;
+  const int team_base = lane - t;
+  for (int b0 = 0; ballot(b0 < np) != 0ull; b0 += PER) {
+    const int b = b0 + team;
+    const bool own = team < PER && b < np;
+    const int st = own ? (int)L.pend_st[cur][b] : 0;
+    const int sz = own ? (int)L.pend_sz[cur][b] : 0;
+    const K x = own ? L.key[st + ((2 * t + 1) * sz) / (2 * NS)] : K(0);
+    // rank of x in the team's sample: smaller keys, plus equal keys of lower lanes
+    int rank = 0;
+#pragma unroll 1
+    for (int u = 0; u < NS; ++u) {
+      K y;
+      if constexpr (sizeof(K) == 8) {
+        const uint32_t lo = read_lane((uint32_t)x, team_base + u);
+        const uint32_t hi = read_lane((uint32_t)(x >> 32), team_base + u);
+        y = ((K)hi << 32) | lo;
+      } else {
+        y = read_lane(x, team_base + u);
+      }
+      rank += (y < x || (y == x && u < t)) ? 1 : 0;
     }
-#pragma unroll
-    for (int t = 0; t < 16; ++t) L.cnt[gl][t] = 0;
-    L.deg[gl] = lo_s == hi_s ? 1 : 0;
+    if (own) {
+      L.sample[b][rank] = x;
+      L.cnt[b][t] = 0;
+      if (t < 16 - NS) L.cnt[b][NS + t] = 0;
+    }
+    wave_lds_sync();
+    // all k-1 splitters equal: the smallest (rank A) equals the largest (rank A*(k-1))
+    if (own && t == 0) L.deg[b] = L.sample[b][A - 1] == L.sample[b][A * (KB - 1) - 1] ? 1 : 0;
   }
 }
 
@@ -414,11 +432,12 @@ __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint
       break;
     }
     const int kk = level == 0 ? k0 : 4;
-    const int a = oversampling(kk);
-    if (a * kk == 12)
-      sample_phase<F, 12>(L, cur, np, kk, a);
+    if (kk == 16)
+      sample_phase<F, 16>(L, cur, np);
+    else if (kk == 8)
+      sample_phase<F, 8>(L, cur, np);
     else
-      sample_phase<F, 16>(L, cur, np, kk, a);
+      sample_phase<F, 4>(L, cur, np);
     wave_lds_sync();
     int npn = 0;
     if (level == 0) {

@@ -32,6 +32,7 @@
 // counts to the host, then one ordinary launch per non-empty class.
 #pragma once
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -52,8 +53,9 @@ constexpr int kSortWaves = kSortThreads / kWave;
 // ctrl layout (uint32 words)
 constexpr int kCtrlCount = 0;        // [kClasses] segments per class
 constexpr int kCtrlStart = 32;       // [kClasses] start of each class list
-constexpr int kCtrlTile = 64;        // tile counter of the persistent kernel
-constexpr int kCtrlWords = 128;
+constexpr int kCtrlTile = 128;       // tile counters: kind set k, partition p at kCtrlTile + (8k + p) * 32
+constexpr int kTileParts = 8;        // counter partitions (one 128-byte line each)
+constexpr int kCtrlWords = kCtrlTile + 5 * kTileParts * 32;
 
 __device__ __forceinline__ int size_class(int sz) {
   if (sz < 2) return sz >= 0 ? -1 : -3;  // -1: nothing to do, -3: bad offsets
@@ -62,6 +64,17 @@ __device__ __forceinline__ int size_class(int sz) {
   if (sz <= 128) return 16;
   if (sz <= kMaxN) return 17;
   return -2;  // too big
+}
+
+// Rounds of RSS lane groups per tile for class c: at most `rounds`, and few
+// enough that the class still has about eight tiles per resident wave (a
+// class with few segments would otherwise leave most waves idle).
+__host__ __device__ __forceinline__ int class_rounds(int c, int count, int rounds, int waves) {
+  if (c < kNetClasses) return 1;
+  const int groups = c == 15 ? 4 : (c == 16 ? 2 : 1);
+  const int per = groups * waves * 8;
+  const int r = count / (per > 0 ? per : 1);
+  return r < 1 ? 1 : (r > rounds ? rounds : r);
 }
 
 // Tile size (segments) of a class; rounds = RSS group rounds per tile.
@@ -168,24 +181,46 @@ struct SortArgs {
   const int32_t* offsets;
   const int32_t* ids;
   const uint32_t* ctrl;
-  int rounds;
+  int rounds;     // maximum RSS group rounds per tile
+  int waves;      // resident waves of a per-class launch (plain baseline)
   int k0[3];
   int interleave;  // alternate RSS and network tiles in the persistent kernel
 };
 
-// Runs tile `tile_in_class` of class c.
-template <int F, class K, bool V>
+// Kind sets of the persistent kernels: every class (one kernel holding every
+// handler), the network classes, or one RSS class (17..64, 65..128, 129..256).
+constexpr int kKindAll = 0, kKindNet = 1, kKindRss16 = 2, kKindRss32 = 3, kKindRss64 = 4, kKinds = 5;
+
+__host__ __device__ __forceinline__ bool in_kind(int c, int ks) {
+  if (ks == kKindAll) return true;
+  if (ks == kKindNet) return c < kNetClasses;
+  return c == kNetClasses + (ks - kKindRss16);
+}
+
+// Runs tile `tile_in_class` of class c (only the handlers of kind set KS are
+// compiled in).
+template <int F, class K, bool V, int KS>
 __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint32_t* vals, const SortArgs& a,
-                                         K flip, int c, int tile_in_class, int count, int list) {
-  const int first = tile_in_class * class_tile(c, a.rounds);
-  if (c < kNetClasses) {
-    net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
-  } else if (c == 15) {
-    rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[0]);
-  } else if (c == 16) {
-    rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[1]);
-  } else {
-    rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[2]);
+                                         K flip, int c, int tile_in_class, int count, int list, int waves) {
+  const int rounds = class_rounds(c, count, a.rounds, waves);
+  const int first = tile_in_class * class_tile(c, rounds);
+  if constexpr (KS == kKindAll || KS == kKindNet) {
+    if (c < kNetClasses) {
+      net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
+      return;
+    }
+  }
+  if constexpr (KS == kKindAll || KS == kKindRss16) {
+    if (c == 15)
+      rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0]);
+  }
+  if constexpr (KS == kKindAll || KS == kKindRss32) {
+    if (c == 16)
+      rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1]);
+  }
+  if constexpr (KS == kKindAll || KS == kKindRss64) {
+    if (c == 17)
+      rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2]);
   }
 }
 
@@ -194,13 +229,17 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint3
 // tile first) and the network classes; with interleaving, RSS and network
 // tiles alternate while both remain, so memory-bound network tiles overlap
 // with ALU/LDS-bound RSS tiles on every CU.
-__device__ __forceinline__ int class_tiles(const uint32_t* ctrl, int c, int rounds) {
-  const int ts = class_tile(c, rounds);
-  return ((int)ctrl[kCtrlCount + c] + ts - 1) / ts;
+template <int KS>
+__device__ __forceinline__ int class_tiles(const uint32_t* ctrl, int c, int rounds, int waves) {
+  if (!in_kind(c, KS)) return 0;
+  const int count = (int)ctrl[kCtrlCount + c];
+  const int ts = class_tile(c, class_rounds(c, count, rounds, waves));
+  return (count + ts - 1) / ts;
 }
 
-__device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rounds, int t_rss, int t_net,
-                                            bool interleave, int& cls, int& idx) {
+template <int KS>
+__device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rounds, int waves, int t_rss,
+                                            int t_net, bool interleave, int& cls, int& idx) {
   int list_pos;  // position in the concatenated class order
   if (interleave) {
     const int both = 2 * min(t_rss, t_net);
@@ -223,7 +262,7 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
   int acc = 0;
   for (int o = 0; o < kClasses; ++o) {
     const int c = class_at(o);
-    const int n = class_tiles(ctrl, c, rounds);
+    const int n = class_tiles<KS>(ctrl, c, rounds, waves);
     if (list_pos < acc + n) {
       cls = c;
       idx = list_pos - acc;
@@ -233,45 +272,110 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
   }
 }
 
-// Waves per SIMD the persistent kernel is compiled for: its register budget.
-// It holds every handler, so unconstrained it would take more registers than
-// the largest of them and lose occupancy, which the latency-bound RSS tiles
-// need.
-template <class K, bool V> struct PersistWaves {
-  static constexpr int value = sizeof(K) == 4 ? (V ? 4 : 5) : (V ? 3 : 4);
+// Waves per SIMD a persistent kernel is compiled for: its register budget.
+// The kernel holding every handler would otherwise take more registers than
+// the largest of them and lose the occupancy that the latency-bound RSS
+// tiles need; the single-kind kernels keep their natural register count.
+template <class K, bool V, int KS> struct PersistWaves {
+  static constexpr int value = KS == kKindAll ? (sizeof(K) == 4 ? (V ? 4 : 5) : (V ? 3 : 4))
+                               : KS == kKindNet ? 1
+                               : (sizeof(K) == 4 && !V) ? 6 : 1;
 };
 
-// Persistent kernel: waves claim tiles (chunk at a time, one atomic) until all
-// are done.
-template <int F, class K, bool V>
-__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(PersistWaves<K, V>::value)))
+template <class K, bool V, int KS> struct PersistLds {
+  static constexpr size_t kBytes = KS == kKindNet     ? 16
+                                   : KS == kKindRss16 ? 4 * sizeof(GroupLds<K, V, 16>)
+                                   : KS == kKindRss32 ? 2 * sizeof(GroupLds<K, V, 32>)
+                                   : KS == kKindRss64 ? sizeof(GroupLds<K, V, 64>)
+                                                      : WaveLds<K, V>::kBytes;
+};
+
+// Persistent kernel over the classes of kind set KS: waves run tiles until all
+// are done.  A single-class kernel indexes its tiles directly.
+template <int F, class K, bool V, int KS>
+__global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(PersistWaves<K, V, KS>::value)))
 seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip,
                       int chunk) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][WaveLds<K, V>::kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][PersistLds<K, V, KS>::kBytes];
   const int wave = threadIdx.x / kWave;
+  const int waves = (int)gridDim.x * kSortWaves;
+  constexpr bool kSingle = KS >= kKindRss16;
+  constexpr int kFixedClass = kSingle ? kNetClasses + (KS - kKindRss16) : 0;
   // tiles of the RSS classes and of the network classes (wave-uniform)
   int t_rss = 0, t_net = 0;
-  for (int c = 0; c < kClasses; ++c) {
-    const int n = class_tiles(a.ctrl, c, a.rounds);
-    if (c >= kNetClasses)
-      t_rss += n;
-    else
-      t_net += n;
-  }
-  const int total = t_rss + t_net;
-  while (true) {
-    int t0 = 0;
-    if (lane_id() == 0) t0 = (int)atomicAdd(&ctrl[kCtrlTile], (uint32_t)chunk);
-    t0 = __builtin_amdgcn_readfirstlane(t0);
-    if (t0 >= total) break;
-    const int t1 = min(t0 + chunk, total);
-    for (int t = t0; t < t1; ++t) {
-      int c, idx;
-      locate_tile(t, a.ctrl, a.rounds, t_rss, t_net, a.interleave != 0, c, idx);
-      run_tile<F, K, V>(lds[wave], keys, vals, a, flip, c, idx, (int)a.ctrl[kCtrlCount + c],
-                        (int)a.ctrl[kCtrlStart + c]);
+  if constexpr (kSingle) {
+    t_rss = class_tiles<KS>(a.ctrl, kFixedClass, a.rounds, waves);
+  } else {
+    for (int c = 0; c < kClasses; ++c) {
+      const int n = class_tiles<KS>(a.ctrl, c, a.rounds, waves);
+      if (c >= kNetClasses)
+        t_rss += n;
+      else
+        t_net += n;
     }
   }
+  // the network-only kernel keeps its class prefix in registers
+  int net_first[kNetClasses + 1];
+  if constexpr (KS == kKindNet) {
+    int acc = 0;
+#pragma unroll
+    for (int o = 0; o < kNetClasses; ++o) {
+      net_first[o] = acc;
+      acc += class_tiles<KS>(a.ctrl, class_at(3 + o), a.rounds, waves);
+    }
+    net_first[kNetClasses] = acc;
+  }
+  const int total = t_rss + t_net;
+  const int fixed_count = kSingle ? (int)a.ctrl[kCtrlCount + kFixedClass] : 0;
+  const int fixed_list = kSingle ? (int)a.ctrl[kCtrlStart + kFixedClass] : 0;
+  // Tiles are handed out round-robin by wave index, except the last ones
+  // (two per wave), which waves claim from an atomic counter as they finish so
+  // that uneven tiles do not leave a tail.  (Claiming every tile atomically
+  // costs more: the counter is shared by all XCDs.)
+  auto process = [&](int t) {
+    if constexpr (kSingle) {
+      run_tile<F, K, V, KS>(lds[wave], keys, vals, a, flip, kFixedClass, t, fixed_count, fixed_list, waves);
+    } else if constexpr (KS == kKindNet) {
+      int c = 0, idx = 0;
+#pragma unroll
+      for (int o = 0; o < kNetClasses; ++o) {
+        if (t >= net_first[o] && t < net_first[o + 1]) {
+          c = class_at(3 + o);
+          idx = t - net_first[o];
+        }
+      }
+      run_tile<F, K, V, KS>(lds[wave], keys, vals, a, flip, c, idx, (int)a.ctrl[kCtrlCount + c],
+                            (int)a.ctrl[kCtrlStart + c], waves);
+    } else {
+      int c, idx;
+      locate_tile<KS>(t, a.ctrl, a.rounds, waves, t_rss, t_net, a.interleave != 0, c, idx);
+      run_tile<F, K, V, KS>(lds[wave], keys, vals, a, flip, c, idx, (int)a.ctrl[kCtrlCount + c],
+                            (int)a.ctrl[kCtrlStart + c], waves);
+    }
+  };
+  // Tiles t = part + 8*i belong to partition part = blockIdx % 8; within a
+  // partition the waves take tiles round-robin, and the last ones (half a
+  // tile per wave) are claimed from the partition's own counter.
+  const int part = (int)blockIdx.x % kTileParts;
+  const int part_blocks = ((int)gridDim.x - part + kTileParts - 1) / kTileParts;
+  const int part_waves = part_blocks * kSortWaves;
+  const int wi = ((int)blockIdx.x / kTileParts) * kSortWaves + wave;
+  const int part_tiles = (total - part + kTileParts - 1) / kTileParts;
+  const int static_end = part_tiles - min(part_tiles, part_waves / 2);
+  uint32_t* counter = &ctrl[kCtrlTile + (KS * kTileParts + part) * 32];
+  int i = wi;
+  while (true) {
+    if (i >= static_end) {  // dynamic tail: claim the next tile of the partition
+      int c0 = 0;
+      if (lane_id() == 0) c0 = (int)atomicAdd(counter, 1u);
+      i = static_end + __builtin_amdgcn_readfirstlane(c0);
+      if (i >= part_tiles) break;
+    }
+    process(part + kTileParts * i);
+    i = i < static_end ? i + part_waves : static_end;
+  }
+  (void)chunk;
+  (void)net_first;
 }
 
 // Plain baseline: one launch per class, tile = blockIdx * waves + wave.  The
@@ -285,15 +389,16 @@ seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, 
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][KIND == 0 ? 16 : WaveLds<K, V>::kBytes];
   const int wave = threadIdx.x / kWave;
   const int tile = blockIdx.x * kSortWaves + wave;
-  const int first = tile * class_tile(c, a.rounds);
+  const int rounds = class_rounds(c, count, a.rounds, a.waves);
+  const int first = tile * class_tile(c, rounds);
   if constexpr (KIND == 0) {
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
   } else if constexpr (KIND == 1) {
-    rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[0]);
+    rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0]);
   } else if constexpr (KIND == 2) {
-    rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[1]);
+    rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1]);
   } else {
-    rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, a.rounds, flip, a.k0[2]);
+    rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2]);
   }
 }
 
@@ -303,8 +408,9 @@ struct GraphEntry {
   int key = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t nodes[4] = {nullptr, nullptr, nullptr, nullptr};  // count, scan, scatter, sort
-  int persist_blocks = 0;
+  hipGraphNode_t nodes[7] = {};  // count, scan, scatter, then the persistent kernel(s)
+  int nnodes = 0;
+  int persist_blocks[kKinds] = {};
 };
 
 struct SegmentedCache {
@@ -323,12 +429,12 @@ SegmentedCache* workspace_for(DeviceCtx* c, hipStream_t s);
 // Grows the workspace's segment-id list to hold nseg ids (caller holds ws->mu).
 hipError_t ensure_workspace(SegmentedCache* ws, int32_t nseg);
 
-template <int F, class K, bool V>
+template <int F, class K, bool V, int KS>
 static int persistent_blocks(DeviceCtx* c) {
   int occ = tuning().persist_occ;
   if (occ <= 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_persistent_kernel<F, K, V>, kSortThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_persistent_kernel<F, K, V, KS>, kSortThreads, 0) !=
             hipSuccess ||
         nb <= 0)
       nb = 2;
@@ -343,6 +449,7 @@ inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
   a.ids = s->ids;
   a.ctrl = s->ctrl;
   a.rounds = tuning().rss_rounds;
+  a.waves = 1;
   a.k0[0] = tuning().rss_k[0];
   a.k0[1] = tuning().rss_k[1];
   a.k0[2] = tuning().rss_k[2];
@@ -350,7 +457,9 @@ inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
   return a;
 }
 
-// The four kernels with their arguments, as launch parameter blocks.
+// The kernels of one call with their arguments, as launch parameter blocks:
+// count, scan, scatter, then either the persistent kernel over every class or
+// (split) the network-class kernel followed by the RSS-class kernel.
 template <int F, class K, bool V>
 struct SegLaunch {
   // argument storage (addresses handed to HIP)
@@ -372,7 +481,16 @@ struct SegLaunch {
   void* p_scan[3];
   void* p_scatter[5];
   void* p_sort[6];
-  int persist_blocks;
+  bool split;
+  int persist_blocks[kKinds];  // grid of the persistent kernel per kind set
+
+  int nnodes() const { return split ? 7 : 4; }
+  // kind set of node i >= 3: network classes, then the RSS classes largest first
+  int node_kind(int i) const {
+    if (!split) return kKindAll;
+    static constexpr int order[4] = {kKindNet, kKindRss64, kKindRss32, kKindRss16};
+    return order[i - 3];
+  }
 
   void fill(DeviceCtx* c, SegmentedCache* s, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
     offsets = off;
@@ -395,6 +513,16 @@ struct SegLaunch {
     p_scatter[4] = &ids;
     p_sort[0] = &keys; p_sort[1] = &vals; p_sort[2] = &args; p_sort[3] = &ctrl; p_sort[4] = &flip;
     p_sort[5] = &chunk;
+  }
+
+  static void* kernel_of(int ks) {
+    switch (ks) {
+      case kKindNet: return (void*)seg_persistent_kernel<F, K, V, kKindNet>;
+      case kKindRss16: return (void*)seg_persistent_kernel<F, K, V, kKindRss16>;
+      case kKindRss32: return (void*)seg_persistent_kernel<F, K, V, kKindRss32>;
+      case kKindRss64: return (void*)seg_persistent_kernel<F, K, V, kKindRss64>;
+      default: return (void*)seg_persistent_kernel<F, K, V, kKindAll>;
+    }
   }
 
   hipKernelNodeParams node(int i) {
@@ -420,12 +548,14 @@ struct SegLaunch {
         p.blockDim = dim3(kBinThreads);
         p.kernelParams = p_scatter;
         break;
-      default:
-        p.func = (void*)seg_persistent_kernel<F, K, V>;
-        p.gridDim = dim3(persist_blocks);
+      default: {
+        const int ks = node_kind(i);
+        p.func = kernel_of(ks);
+        p.gridDim = dim3(persist_blocks[ks]);
         p.blockDim = dim3(kSortThreads);
         p.kernelParams = p_sort;
         break;
+      }
     }
     return p;
   }
@@ -441,24 +571,34 @@ struct SegLaunch {
   hipError_t launch_direct(hipStream_t s) {
     hipError_t e = launch_binning(s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((seg_persistent_kernel<F, K, V>), dim3(persist_blocks), dim3(kSortThreads), 0, s, keys,
-                       vals, args, ctrl, flip, chunk);
+    for (int i = 3; i < nnodes(); ++i) {
+      hipKernelNodeParams p = node(i);
+      hipError_t le = hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, 0, s);
+      if (le != hipSuccess) return le;
+    }
     return hipGetLastError();
   }
 };
 
 template <int F, class K, bool V>
-static hipError_t run_plain(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
+static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
+  // resident waves of one per-class launch (largest RSS class kernel)
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_class_kernel<F, K, V, 3>, kSortThreads, 0) !=
+          hipSuccess ||
+      nb <= 0)
+    nb = 2;
+  L.args.waves = nb * c->num_cus * kSortWaves;
   hipError_t e = L.launch_binning(s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, kCtrlWords * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, (kCtrlStart + kClasses) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   for (int o = 0; o < kClasses; ++o) {
     const int cls = class_at(o);
     const int count = (int)sc->host_ctrl[kCtrlCount + cls];
     if (count == 0) continue;
-    const int ts = class_tile(cls, L.args.rounds);
+    const int ts = class_tile(cls, class_rounds(cls, count, L.args.rounds, L.args.waves));
     const int tiles = (count + ts - 1) / ts;
     const int blocks = (tiles + kSortWaves - 1) / kSortWaves;
     const int list = (int)sc->host_ctrl[kCtrlStart + cls];
@@ -480,17 +620,18 @@ static hipError_t run_plain(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream
 
 template <int F, class K, bool V>
 static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
-  const int key = (int)sizeof(K) * 4 + (V ? 2 : 0) + F;
+  const int key = ((int)sizeof(K) * 4 + (V ? 2 : 0) + F) * 2 + (L.split ? 1 : 0);
   GraphEntry* g = nullptr;
   for (GraphEntry& ge : sc->graphs)
-    if (ge.key == key && ge.persist_blocks == L.persist_blocks) g = &ge;
+    if (ge.key == key && std::equal(ge.persist_blocks, ge.persist_blocks + kKinds, L.persist_blocks)) g = &ge;
   hipError_t e = hipSuccess;
   if (!g) {
     GraphEntry ne;
     ne.key = key;
-    ne.persist_blocks = L.persist_blocks;
+    ne.nnodes = L.nnodes();
+    std::copy(L.persist_blocks, L.persist_blocks + kKinds, ne.persist_blocks);
     e = hipGraphCreate(&ne.graph, 0);
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    for (int i = 0; i < ne.nnodes && e == hipSuccess; ++i) {
       hipKernelNodeParams p = L.node(i);
       e = hipGraphAddKernelNode(&ne.nodes[i], ne.graph, i ? &ne.nodes[i - 1] : nullptr, i ? 1 : 0, &p);
     }
@@ -502,7 +643,7 @@ static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream
     sc->graphs.push_back(ne);
     g = &sc->graphs.back();
   } else {
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    for (int i = 0; i < g->nnodes && e == hipSuccess; ++i) {
       hipKernelNodeParams p = L.node(i);
       e = hipGraphExecKernelNodeSetParams(g->exec, g->nodes[i], &p);
     }
@@ -515,11 +656,20 @@ template <int F, class K, bool V>
 static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets,
                           int32_t nseg, K flip, int mode, hipStream_t s) {
   SegLaunch<F, K, V> L;
-  L.persist_blocks = persistent_blocks<F, K, V>(c);
+  L.split = tuning().persist_split != 0;
+  for (int& b : L.persist_blocks) b = 0;
+  if (L.split) {
+    L.persist_blocks[kKindNet] = persistent_blocks<F, K, V, kKindNet>(c);
+    L.persist_blocks[kKindRss16] = persistent_blocks<F, K, V, kKindRss16>(c);
+    L.persist_blocks[kKindRss32] = persistent_blocks<F, K, V, kKindRss32>(c);
+    L.persist_blocks[kKindRss64] = persistent_blocks<F, K, V, kKindRss64>(c);
+  } else {
+    L.persist_blocks[kKindAll] = persistent_blocks<F, K, V, kKindAll>(c);
+  }
   L.fill(c, ws, keys, vals, offsets, nseg, flip);
   hipError_t e;
   if (mode == 2)
-    e = run_plain(ws, L, s);
+    e = run_plain(c, ws, L, s);
   else if (mode == 1)
     e = L.launch_direct(s);
   else

@@ -70,7 +70,7 @@ seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restr
       ctrl[kCtrlStart + c] = st;
       st += tot[c];
     }
-    ctrl[kCtrlTile] = 0;
+    for (int k = 0; k < kKinds * kTileParts; ++k) ctrl[kCtrlTile + k * 32] = 0;
   }
 }
 
