@@ -129,10 +129,10 @@ const char *ss_strerror(ss_status status);
  *                  Sample Sort level for arrays of 17..64 keys
  *   "rss_k_mid"    same for arrays of 65..128 keys
  *   "rss_k_large"  same for arrays of 129..256 keys
- *   "tile_chunk"   tiles claimed per atomic by the persistent kernel (1..64)
  *   "persist_occ"  work-groups per CU of the persistent grid (0 = as many as
  *                  fit, 1..16)
- *   "rss_rounds"   rounds of lane groups per RSS tile in segmented sorts (1..16)
+ *   "rss_rounds"   most rounds of lane groups per RSS tile in segmented sorts
+ *                  (1..16; fewer when a size class has few segments)
  *   "interleave"   1: the persistent kernel alternates RSS and network tiles
  *   "persist_split" 1: a persistent kernel for the network classes, then one
  *                  per RSS size class (each with only its own code and

@@ -1,9 +1,9 @@
 """Autotuner for the library's variant choices (run on the GPU).
 
 Knobs (see include/smallsort.h): network family; first-level bucket count of
-Register Sample Sort per size class; rounds of lane groups per RSS tile, tiles
-per atomic claim, tile interleaving and work-groups per CU of the persistent
-ragged kernel.  The paper found the best variant and RSS parameters to differ
+Register Sample Sort per size class; the most rounds of lane groups per RSS
+tile, one persistent kernel per kind or one for all, tile interleaving (single
+kernel) and work-groups per CU of the persistent ragged kernels.  The paper found the best variant and RSS parameters to differ
 from machine to machine (Sections 4.2 and 4.5); here they are measured on the
 GPU at hand.
 
@@ -120,7 +120,6 @@ SPACE = [
     ("rss_k_mid", [4, 8, 16], "rss"),
     ("rss_k_large", [4, 8, 16], "rss"),
     ("rss_rounds", [2, 4, 8, 16], "ragged"),
-    ("tile_chunk", [1, 2, 4, 8, 16], "ragged"),
     ("persist_split", [0, 1], "ragged"),
     ("interleave", [0, 1], "ragged"),
     ("persist_occ", [0, 1, 2, 3], "ragged"),

@@ -294,8 +294,7 @@ template <class K, bool V, int KS> struct PersistLds {
 // are done.  A single-class kernel indexes its tiles directly.
 template <int F, class K, bool V, int KS>
 __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(PersistWaves<K, V, KS>::value)))
-seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip,
-                      int chunk) {
+seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][PersistLds<K, V, KS>::kBytes];
   const int wave = threadIdx.x / kWave;
   const int waves = (int)gridDim.x * kSortWaves;
@@ -374,7 +373,6 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
     process(part + kTileParts * i);
     i = i < static_end ? i + part_waves : static_end;
   }
-  (void)chunk;
   (void)net_first;
 }
 
@@ -476,11 +474,10 @@ struct SegLaunch {
   uint32_t* vals;
   SortArgs args;
   K flip;
-  int chunk;
   void* p_count[4];
   void* p_scan[3];
   void* p_scatter[5];
-  void* p_sort[6];
+  void* p_sort[5];
   bool split;
   int persist_blocks[kKinds];  // grid of the persistent kernel per kind set
 
@@ -506,13 +503,11 @@ struct SegLaunch {
     vals = v;
     args = make_args(off, s);
     flip = fl;
-    chunk = tuning().tile_chunk;
     p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status;
     p_scan[0] = &blockhist; p_scan[1] = &nblocks; p_scan[2] = &ctrl;
     p_scatter[0] = &offsets; p_scatter[1] = &nseg; p_scatter[2] = &blockbase; p_scatter[3] = &ctrl_c;
     p_scatter[4] = &ids;
     p_sort[0] = &keys; p_sort[1] = &vals; p_sort[2] = &args; p_sort[3] = &ctrl; p_sort[4] = &flip;
-    p_sort[5] = &chunk;
   }
 
   static void* kernel_of(int ks) {
