@@ -54,9 +54,9 @@ def parse():
 
 # --- counters --------------------------------------------------------------------
 
-# source files each profiled kernel is built from
+# source files that define each profiled kernel's device code
 KERNEL_SOURCES = {
-    "fixed_tile_kernel<n=16,u32>": ("fixed.hip", "common.hpp", "networks_gen.hpp", "internal.hpp"),
+    "fixed_tile_kernel<n=16,u32>": ("fixed.hip", "common.hpp", "networks_gen.hpp"),
 }
 
 
