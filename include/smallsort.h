@@ -132,7 +132,7 @@ const char *ss_strerror(ss_status status);
  *   "persist_occ"  work-groups per CU of the persistent grid (0 = as many as
  *                  fit, 1..16)
  *   "rss_rounds"   most rounds of lane groups per RSS tile in segmented sorts
- *                  (1..16; fewer when a size class has few segments)
+ *                  (1..64; fewer when a size class has few segments)
  *   "interleave"   1: the persistent kernel alternates RSS and network tiles
  *   "persist_split" 1: a persistent kernel for the network classes, then one
  *                  per RSS size class (each with only its own code and

@@ -3,9 +3,14 @@
 Knobs (see include/smallsort.h): network family; first-level bucket count of
 Register Sample Sort per size class; the most rounds of lane groups per RSS
 tile, one persistent kernel per kind or one for all, tile interleaving (single
-kernel) and work-groups per CU of the persistent ragged kernels.  The paper found the best variant and RSS parameters to differ
-from machine to machine (Sections 4.2 and 4.5); here they are measured on the
-GPU at hand.
+kernel) and work-groups per CU of the persistent ragged kernels.  The paper
+found the best variant and RSS parameters to differ from machine to machine
+(Sections 4.2 and 4.5); here they are measured on the GPU at hand.
+
+Workloads: fixed-size arrays of 4..16 keys (family); one CSR batch per RSS
+size class (its bucket count); for the segmented-sort knobs the sum of the
+10^7-segment ragged batch with payload and the 2^20-array RSS-only batch, at
+the sizes the benchmark uses (a quarter of each with --quick).
 
 Method: coordinate descent.  For each knob in turn every allowed value is
 timed on a representative workload with the other knobs fixed, and the
@@ -80,10 +85,14 @@ class Workloads:
             off = inputs.offsets_from_sizes(inputs.csr_sizes((1 << 18) // scale, lo, hi, seed=hi))
             k = torch.from_numpy(inputs.random_keys(np.uint64, int(off[-1]), seed=lo)).cuda()
             self.rss[knob] = (k, k.clone(), torch.from_numpy(off).cuda())
-        # ragged batch shaped like the 10^7-segment benchmark (fewer segments)
-        k, v, off = inputs.config4(nseg=2_000_000 // scale, seed=44)
+        # ragged batch of the 10^7-segment benchmark (a quarter with --quick)
+        k, v, off = inputs.config4(nseg=10_000_000 // scale, seed=44)
         self.ragged = (torch.from_numpy(k).cuda(), torch.from_numpy(v).cuda(), torch.from_numpy(off).cuda())
         self.ragged_src = tuple(t.clone() for t in self.ragged[:2])
+        # RSS-only batch of the 2^20-array benchmark: int32 arrays of 17..256 keys
+        k, off = inputs.config3(nseg=(1 << 20) // scale, dist="uniform", seed=7)
+        k = torch.from_numpy(k).cuda()
+        self.rss_all = (k, k.clone(), torch.from_numpy(off).cuda())
         torch.cuda.synchronize()
 
     def time_family(self, reps):
@@ -101,7 +110,7 @@ class Workloads:
         k, src, off = self.rss[knob]
         return _timer(lambda: segmented_sort(k, off), lambda: k.copy_(src), reps)
 
-    def time_ragged(self, reps, mode=0):
+    def time_ragged_only(self, reps, mode=0):
         from . import segmented_sort
         k, v, off = self.ragged
 
@@ -111,6 +120,15 @@ class Workloads:
 
         return _timer(lambda: segmented_sort(k, off, v, mode=mode), restore, reps)
 
+    def time_rss_all(self, reps, mode=0):
+        from . import segmented_sort
+        k, src, off = self.rss_all
+        return _timer(lambda: segmented_sort(k, off, mode=mode), lambda: k.copy_(src), reps)
+
+    def time_ragged(self, reps, mode=0):
+        """Objective of the segmented-sort knobs: ragged batch + RSS-only batch."""
+        return self.time_ragged_only(reps, mode) + self.time_rss_all(reps, mode)
+
 
 NOISE = 0.01
 
@@ -119,7 +137,7 @@ SPACE = [
     ("rss_k_small", [4, 8, 16], "rss"),
     ("rss_k_mid", [4, 8, 16], "rss"),
     ("rss_k_large", [4, 8, 16], "rss"),
-    ("rss_rounds", [2, 4, 8, 16], "ragged"),
+    ("rss_rounds", [4, 8, 16, 32], "ragged"),
     ("persist_split", [0, 1], "ragged"),
     ("interleave", [0, 1], "ragged"),
     ("persist_occ", [0, 1, 2, 3], "ragged"),
@@ -152,23 +170,11 @@ def tune(quick=False, reps=5, log=print):
         best[name] = choice
         report[name] = {"ms": {str(k): v for k, v in results.items()}, "best": choice}
         log(f"{name} -> {choice}")
-    report["ragged_plain_ms"] = w.time_ragged(reps, mode=2)
-    report["ragged_graph_ms"] = w.time_ragged(reps, mode=0)
+    # tuned persistent graph form vs one launch per size class
+    for mode, name in ((0, "graph"), (2, "plain")):
+        report[f"ragged_{name}_ms"] = w.time_ragged_only(reps, mode)
+        report[f"rss_{name}_ms"] = w.time_rss_all(reps, mode)
     return best, report
-
-
-def compare_modes(reps=5):
-    """Graph vs plain on the RSS-only batch (all three RSS classes) and the ragged batch."""
-    import torch
-    from . import inputs, segmented_sort, MODE_AUTO, MODE_PLAIN
-    off = inputs.offsets_from_sizes(inputs.csr_sizes(1 << 19, 17, 256, seed=7))
-    k = torch.from_numpy(inputs.random_keys(np.int32, int(off[-1]), seed=7)).cuda()
-    src = k.clone()
-    to = torch.from_numpy(off).cuda()
-    out = {}
-    for name, mode in (("graph", MODE_AUTO), ("plain", MODE_PLAIN)):
-        out[f"rss_{name}_ms"] = _timer(lambda: segmented_sort(k, to, mode=mode), lambda: k.copy_(src), reps)
-    return out
 
 
 def main():
@@ -183,7 +189,6 @@ def main():
     arch, rocm = system_tag()
     t0 = time.time()
     best, report = tune(quick=args.quick, reps=args.reps, log=lambda s: print(s, flush=True))
-    report.update(compare_modes(args.reps))
     print(json.dumps({k: v for k, v in report.items() if k.endswith("_ms")}), flush=True)
     out = args.out or default_path(arch)
     doc = dict(best)

@@ -135,7 +135,7 @@ static std::vector<TuneEntry> tune_table() {
       {"rss_k_mid", &t.rss_k[1], 4, 16, true},
       {"rss_k_large", &t.rss_k[2], 4, 16, true},
       {"persist_occ", &t.persist_occ, 0, 16, false},
-      {"rss_rounds", &t.rss_rounds, 1, 16, false},
+      {"rss_rounds", &t.rss_rounds, 1, 64, false},
       {"interleave", &t.interleave, 0, 1, false},
       {"persist_split", &t.persist_split, 0, 1, false},
   };

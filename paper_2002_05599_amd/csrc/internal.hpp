@@ -11,7 +11,7 @@ struct Tuning {
   int family = 0;        // network family for n <= 16 (0 fewest comparators, 1 Bose-Nelson)
   int rss_k[3] = {4, 8, 16};  // level-0 bucket count for 17..64, 65..128, 129..256 keys
   int persist_occ = 0;   // work-groups per CU for the persistent grid (0 = occupancy limit)
-  int rss_rounds = 8;    // rounds of groups per RSS tile in the segmented kernels
+  int rss_rounds = 16;    // rounds of groups per RSS tile in the segmented kernels
   int interleave = 1;    // persistent kernel alternates RSS and network tiles
   int persist_split = 1;  // 1: one persistent kernel per kind (networks, each RSS class); 0: one for all
 };

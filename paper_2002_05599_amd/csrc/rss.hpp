@@ -49,8 +49,12 @@ template <class K, bool V, int G> struct GroupLds {
   static constexpr int kCap = 4 * G;          // keys per array handled by a G-lane group
   static constexpr int kMaxPend = kCap / 17;  // buckets with more than 16 keys
   static constexpr int kMaxFin = kCap / 2;    // buckets with 2..16 keys
-  K key[kCap];
-  uint32_t val[V ? kCap : 1];
+  // keys (and values) of the array, plus kPad slack entries so that a
+  // 16-wide window starting at any position stays inside the array; the last
+  // entry doubles as the sink for stores that fall outside a bucket
+  static constexpr int kPad = 17;
+  K key[kCap + kPad];
+  uint32_t val[V ? kCap + kPad : 1];
   K sample[kMaxPend][16];          // sorted sample of each pending bucket
   uint32_t cnt[kMaxPend][16];      // per (bucket, child): count, then child offset
   uint8_t nextpb[kMaxPend][16];    // pending index of each child at the next level, or 0xFF
@@ -100,27 +104,36 @@ __device__ __forceinline__ int classify(K e, const K* spl) {
   return TreeDescent<LOGK, K>::run(e, spl, 0);
 }
 
-// Finish the buckets of the finish list with networks of N channels.
+// Finish the buckets of the finish list with networks of N channels.  The
+// N-key window at the bucket start is read unconditionally (the arrays have
+// slack) and the channels beyond the bucket are replaced by the maximum key;
+// stores beyond the bucket go to the sink entry instead of being masked.
 template <int F, int N, class K, bool V, int G>
 __device__ __forceinline__ void finish_buckets(GroupLds<K, V, G>& L, bool ok, int st, int sz) {
+  using Lds = GroupLds<K, V, G>;
   K r[N];
   uint32_t v[N];
+  const int n = ok ? sz : 0;
+  const K* kp = &L.key[st];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const bool in = ok && j < sz;
-    r[j] = in ? L.key[st + j] : KeyTraits<K>::kMax;
-    if constexpr (V) v[j] = in ? L.val[st + j] : 0u;
+    const K x = kp[j];
+    r[j] = j < n ? x : KeyTraits<K>::kMax;
   }
-  if constexpr (V)
+  if constexpr (V) {
+    const uint32_t* vp = &L.val[st];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = vp[j];
     net_sort<F, N>(r, v);
-  else
+  } else {
     net_sort<F, N>(r);
+  }
+  constexpr int kSink = Lds::kCap + Lds::kPad - 1;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    if (ok && j < sz) {
-      L.key[st + j] = r[j];
-      if constexpr (V) L.val[st + j] = v[j];
-    }
+    const int dst = j < n ? st + j : kSink;
+    L.key[dst] = r[j];
+    if constexpr (V) L.val[dst] = v[j];
   }
 }
 

@@ -67,12 +67,17 @@ __device__ __forceinline__ int size_class(int sz) {
 }
 
 // Rounds of RSS lane groups per tile for class c: at most `rounds`, and few
-// enough that the class still has about eight tiles per resident wave (a
-// class with few segments would otherwise leave most waves idle).
-__host__ __device__ __forceinline__ int class_rounds(int c, int count, int rounds, int waves) {
+// enough that the class still has about `tpw` tiles per resident wave (a
+// class with few segments would otherwise leave most waves idle).  The
+// persistent kernels balance their tails dynamically and do best with fewer,
+// larger tiles (kPersistTpw); one launch per class relies on the hardware
+// dispatcher and does best with more (kPlainTpw).
+constexpr int kPersistTpw = 4;
+constexpr int kPlainTpw = 8;
+__host__ __device__ __forceinline__ int class_rounds(int c, int count, int rounds, int waves, int tpw) {
   if (c < kNetClasses) return 1;
   const int groups = c == 15 ? 4 : (c == 16 ? 2 : 1);
-  const int per = groups * waves * 8;
+  const int per = groups * waves * tpw;
   const int r = count / (per > 0 ? per : 1);
   return r < 1 ? 1 : (r > rounds ? rounds : r);
 }
@@ -202,7 +207,7 @@ __host__ __device__ __forceinline__ bool in_kind(int c, int ks) {
 template <int F, class K, bool V, int KS>
 __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint32_t* vals, const SortArgs& a,
                                          K flip, int c, int tile_in_class, int count, int list, int waves) {
-  const int rounds = class_rounds(c, count, a.rounds, waves);
+  const int rounds = class_rounds(c, count, a.rounds, waves, kPersistTpw);
   const int first = tile_in_class * class_tile(c, rounds);
   if constexpr (KS == kKindAll || KS == kKindNet) {
     if (c < kNetClasses) {
@@ -233,7 +238,7 @@ template <int KS>
 __device__ __forceinline__ int class_tiles(const uint32_t* ctrl, int c, int rounds, int waves) {
   if (!in_kind(c, KS)) return 0;
   const int count = (int)ctrl[kCtrlCount + c];
-  const int ts = class_tile(c, class_rounds(c, count, rounds, waves));
+  const int ts = class_tile(c, class_rounds(c, count, rounds, waves, kPersistTpw));
   return (count + ts - 1) / ts;
 }
 
@@ -279,7 +284,9 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
 template <class K, bool V, int KS> struct PersistWaves {
   static constexpr int value = KS == kKindAll ? (sizeof(K) == 4 ? (V ? 4 : 5) : (V ? 3 : 4))
                                : KS == kKindNet ? 1
-                               : (sizeof(K) == 4 && !V) ? 6 : 1;
+                               : (sizeof(K) == 4 && !V) ? 6
+                               : sizeof(K) == 4          ? 5
+                                                         : 4;
 };
 
 template <class K, bool V, int KS> struct PersistLds {
@@ -365,6 +372,7 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
   int i = wi;
   while (true) {
     if (i >= static_end) {  // dynamic tail: claim the next tile of the partition
+      if (static_end == part_tiles) break;
       int c0 = 0;
       if (lane_id() == 0) c0 = (int)atomicAdd(counter, 1u);
       i = static_end + __builtin_amdgcn_readfirstlane(c0);
@@ -387,7 +395,7 @@ seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, 
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][KIND == 0 ? 16 : WaveLds<K, V>::kBytes];
   const int wave = threadIdx.x / kWave;
   const int tile = blockIdx.x * kSortWaves + wave;
-  const int rounds = class_rounds(c, count, a.rounds, a.waves);
+  const int rounds = class_rounds(c, count, a.rounds, a.waves, kPlainTpw);
   const int first = tile * class_tile(c, rounds);
   if constexpr (KIND == 0) {
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
@@ -593,7 +601,7 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
     const int cls = class_at(o);
     const int count = (int)sc->host_ctrl[kCtrlCount + cls];
     if (count == 0) continue;
-    const int ts = class_tile(cls, class_rounds(cls, count, L.args.rounds, L.args.waves));
+    const int ts = class_tile(cls, class_rounds(cls, count, L.args.rounds, L.args.waves, kPlainTpw));
     const int tiles = (count + ts - 1) / ts;
     const int blocks = (tiles + kSortWaves - 1) / kSortWaves;
     const int list = (int)sc->host_ctrl[kCtrlStart + cls];
