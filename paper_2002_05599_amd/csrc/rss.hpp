@@ -4,11 +4,13 @@
 // The array is staged in LDS.  Each level of the recursion handles every
 // pending bucket (more than 16 keys) of the array:
 //
-//   1. sample: one lane per pending bucket picks a*k keys at equidistant
-//      positions floor((2t+1)*size/(2ak)) and sorts them with the network of
-//      a*k channels (Section 3: the splitter sample is sorted by the base-case
-//      sorter); k buckets with oversampling a = 3 for k = 4 (the paper's
-//      "332"), a = 16/k for k = 8 and 16;
+//   1. sample: a team of a*k lanes per pending bucket picks a*k keys at
+//      equidistant positions floor((2t+1)*size/(2ak)), one per lane, and
+//      sorts them by rank (each lane counts the team's keys that precede its
+//      own, ties broken by lane); the paper sorts the sample with its
+//      base-case sorter (Section 3) -- any sort gives the same sorted sample.
+//      k buckets with oversampling a = 3 for k = 4 (the paper's "332"),
+//      a = 16/k for k = 8 and 16;
 //   2. splitters: s_i = S_{a*i} for i = 1..k-1 (Section 3, basic sample
 //      sort);
 //   3. classify: bucket j = #{splitters < e}, i.e. s_j < e <= s_{j+1}, found
@@ -164,10 +166,11 @@ __device__ __forceinline__ void finish_dispatch(GroupLds<K, V, G>& L, bool ok, i
 __host__ __device__ constexpr int oversampling(int k) { return k == 4 ? 3 : 16 / k; }
 
 // Sample of NS = a*k keys (k = KB buckets) at positions
-// floor((2t+1)*size/(2*NS)) of each pending bucket (one lane per bucket),
-// sorted by the NS-channel network; also clears the bucket's child counters
-// and records whether all of its k-1 splitters are equal.
-template <int F, int KB, class K, bool V, int G>
+// floor((2t+1)*size/(2*NS)) of each pending bucket (a team of NS lanes per
+// bucket, one key per lane), sorted by rank within the team; also clears the
+// bucket's child counters and records whether all of its k-1 splitters are
+// equal.
+template <int KB, class K, bool V, int G>
 __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
   constexpr int A = oversampling(KB);
   constexpr int NS = A * KB;
@@ -446,11 +449,11 @@ __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint
     }
     const int kk = level == 0 ? k0 : 4;
     if (kk == 16)
-      sample_phase<F, 16>(L, cur, np);
+      sample_phase<16>(L, cur, np);
     else if (kk == 8)
-      sample_phase<F, 8>(L, cur, np);
+      sample_phase<8>(L, cur, np);
     else
-      sample_phase<F, 4>(L, cur, np);
+      sample_phase<4>(L, cur, np);
     wave_lds_sync();
     int npn = 0;
     if (level == 0) {
