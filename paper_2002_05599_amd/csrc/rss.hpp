@@ -64,9 +64,10 @@ template <class K, bool V, int G> struct GroupLds {
   uint8_t pb[kCap];                // pending bucket of each position, or 0xFF
   uint16_t pend_st[2][kMaxPend];
   uint16_t pend_sz[2][kMaxPend];
-  uint16_t fin_st[kMaxFin];
-  uint16_t fin_sz[kMaxFin];
+  uint16_t fin[kMaxFin];            // finish list: start | size << 9 (start < 512, size <= 16)
 };
+
+__device__ __forceinline__ uint16_t fin_pack(int st, int sz) { return (uint16_t)(st | (sz << 9)); }
 
 // Orders this wave's LDS accesses: DS instructions of one wave execute in
 // order, so only the compiler must be kept from moving accesses across.
@@ -335,8 +336,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     if (own) L.cnt[pq][cq] = off;
     if (is_fin) {
       const int idx = min(nf + (int)__popcll(Fm & below), GroupLds<K, V, G>::kMaxFin - 1);
-      L.fin_st[idx] = (uint16_t)cst;
-      L.fin_sz[idx] = (uint16_t)csz;
+      L.fin[idx] = fin_pack(cst, csz);
     }
     int pidx = 0xFF;
     if (is_pend) {
@@ -407,26 +407,12 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
   }
 }
 
-// Sorts one array of m keys (0 <= m <= 4G) per G-lane group; every lane of
-// the wave must call this (loops are wave-uniform).  gk/gv point at the
-// group's array in global memory; keys are XORed with flip on load and store.
+// Sorts the array of m keys (0 <= m <= 4G) that the group holds in L.key (and
+// L.val), in place in LDS.  Every lane of the wave must call this (loops are
+// wave-uniform).
 template <int F, class K, bool V, int G>
-__device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip, int k0) {
-  const int lane = lane_id();
-  const int gl = lane % G;
-  const int gbase = lane - gl;
-  const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
-  (void)gmask;
-
-  // 1. load (coalesced within the group)
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int i = gl + G * s;
-    if (i < m) {
-      L.key[i] = gk[i] ^ flip;
-      if constexpr (V) L.val[i] = gv[i];
-    }
-  }
+__device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0) {
+  const int gl = lane_id() % G;
   int np = m > 16 ? 1 : 0;
   int nf = (m >= 2 && m <= 16) ? 1 : 0;
   if (gl == 0) {
@@ -434,10 +420,7 @@ __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint
       L.pend_st[0][0] = 0;
       L.pend_sz[0][0] = (uint16_t)m;
     }
-    if (nf) {
-      L.fin_st[0] = 0;
-      L.fin_sz[0] = (uint16_t)m;
-    }
+    if (nf) L.fin[0] = fin_pack(0, m);
   }
   wave_lds_sync();
 
@@ -474,14 +457,33 @@ __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint
   for (int base = 0; ballot(base < nf) != 0ull; base += G) {
     const int b = base + gl;
     const bool ok = b < nf;
-    const int st = ok ? (int)L.fin_st[b] : 0;
-    const int sz = ok ? (int)L.fin_sz[b] : 0;
+    const int fe = ok ? (int)L.fin[b] : 0;
+    const int st = fe & 511;
+    const int sz = fe >> 9;
     const int nmax = (int)wave_max((uint32_t)sz);
     finish_dispatch<F>(L, ok, st, sz, nmax);
   }
   wave_lds_sync();
+}
 
-  // store (coalesced within the group)
+// Global -> LDS (keys XORed with flip), coalesced within the group.
+template <class K, bool V, int G>
+__device__ __forceinline__ void rss_group_load(GroupLds<K, V, G>& L, const K* gk, const uint32_t* gv, int m, K flip) {
+  const int gl = lane_id() % G;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int i = gl + G * s;
+    if (i < m) {
+      L.key[i] = gk[i] ^ flip;
+      if constexpr (V) L.val[i] = gv[i];
+    }
+  }
+}
+
+// LDS -> global (keys XORed with flip), coalesced within the group.
+template <class K, bool V, int G>
+__device__ __forceinline__ void rss_group_store(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip) {
+  const int gl = lane_id() % G;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int i = gl + G * s;
@@ -490,6 +492,17 @@ __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint
       if constexpr (V) gv[i] = L.val[i];
     }
   }
+}
+
+// Loads, sorts and stores one array of m keys per G-lane group; gk/gv point at
+// the group's array in global memory; keys are XORed with flip on load and
+// store.
+template <int F, class K, bool V, int G>
+__device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip, int k0) {
+  rss_group_load(L, gk, gv, m, flip);
+  wave_lds_sync();
+  rss_group_sort_lds<F>(L, m, k0);
+  rss_group_store(L, gk, gv, m, flip);
   wave_lds_sync();
 }
 

@@ -162,22 +162,36 @@ template <class K, bool V> struct WaveLds {
                                                        : (kBytes32 > kBytes64 ? kBytes32 : kBytes64);
 };
 
+// One tile: `rounds` rounds of kWave/G arrays (one per G-lane group).  The
+// segment bounds of up to 64 arrays are fetched at once (one per lane) and
+// handed to the groups with lane permutes, so a round waits for global memory
+// once (its keys) instead of three times (id, bounds, keys).
 template <int F, class K, bool V, int G>
 __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint32_t* vals,
                                          const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
                                          int list, int count, int first, int rounds, K flip, int k0) {
   constexpr int kGroups = kWave / G;
   auto* L = reinterpret_cast<GroupLds<K, V, G>*>(wave_lds);
-  const int g = lane_id() / G;
+  const int lane = lane_id();
+  const int g = lane / G;
+  const int narr = rounds * kGroups;
+  int meta_lo = 0, meta_m = 0;  // lane l: bounds of array a0 + l of the tile
   for (int r = 0; r < rounds; ++r) {
-    const int j = first + r * kGroups + g;
-    int m = 0;
-    int64_t lo = 0;
-    if (j < count) {
-      const int seg = ids[list + j];
-      lo = offsets[seg];
-      m = offsets[seg + 1] - (int)lo;
+    const int a0 = r * kGroups;
+    if ((a0 & (kWave - 1)) == 0) {
+      const int a = a0 + lane;
+      const int j = first + a;
+      meta_lo = 0;
+      meta_m = 0;
+      if (a < narr && j < count) {
+        const int seg = ids[list + j];
+        meta_lo = offsets[seg];
+        meta_m = offsets[seg + 1] - meta_lo;
+      }
     }
+    const int src = (a0 & (kWave - 1)) + g;
+    const int lo = (int)read_lane((uint32_t)meta_lo, src);
+    const int m = (int)read_lane((uint32_t)meta_m, src);
     rss_group_sort<F, K, V, G>(L[g], keys + lo, V ? vals + lo : nullptr, m, flip, k0);
   }
 }
@@ -340,7 +354,8 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
   // costs more: the counter is shared by all XCDs.)
   auto process = [&](int t) {
     if constexpr (kSingle) {
-      run_tile<F, K, V, KS>(lds[wave], keys, vals, a, flip, kFixedClass, t, fixed_count, fixed_list, waves);
+      run_tile<F, K, V, KS>(lds[wave], keys, vals, a, flip, kFixedClass, t, fixed_count, fixed_list,
+                            waves);
     } else if constexpr (KS == kKindNet) {
       int c = 0, idx = 0;
 #pragma unroll
@@ -400,11 +415,14 @@ seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, 
   if constexpr (KIND == 0) {
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
   } else if constexpr (KIND == 1) {
-    rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0]);
+    rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
+                          a.k0[0]);
   } else if constexpr (KIND == 2) {
-    rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1]);
+    rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
+                          a.k0[1]);
   } else {
-    rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2]);
+    rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
+                          a.k0[2]);
   }
 }
 
