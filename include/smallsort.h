@@ -127,8 +127,8 @@ const char *ss_strerror(ss_status status);
  *   "family"       network family: 0 = fewest comparators, 1 = Bose-Nelson
  *   "rss_k_small"  buckets (4, 8 or 16; splitters + 1) of the first Register
  *                  Sample Sort level for arrays of 17..64 keys
- *   "rss_k_mid"    same for arrays of 65..128 keys
- *   "rss_k_large"  same for arrays of 129..256 keys
+ *   "rss_k_mid"    same for arrays of 65..128 keys (4, 8, 16 or 32)
+ *   "rss_k_large"  same for arrays of 129..256 keys (4, 8, 16, 32 or 64)
  *   "persist_occ"  work-groups per CU of the persistent grid (0 = as many as
  *                  fit, 1..16)
  *   "rss_rounds"   most rounds of lane groups per RSS tile in segmented sorts

@@ -135,8 +135,8 @@ NOISE = 0.01
 SPACE = [
     ("family", [0, 1], "family"),
     ("rss_k_small", [4, 8, 16], "rss"),
-    ("rss_k_mid", [4, 8, 16], "rss"),
-    ("rss_k_large", [4, 8, 16], "rss"),
+    ("rss_k_mid", [4, 8, 16, 32], "rss"),
+    ("rss_k_large", [4, 8, 16, 32, 64], "rss"),
     ("rss_rounds", [4, 8, 16, 32], "ragged"),
     ("persist_split", [0, 1], "ragged"),
     ("interleave", [0, 1], "ragged"),

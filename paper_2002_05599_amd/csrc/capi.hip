@@ -124,7 +124,7 @@ struct TuneEntry {
   const char* name;
   int* slot;
   int lo, hi;
-  bool pow2_k;  // must be 4, 8 or 16
+  bool pow2_k;  // a bucket count: a power of two in [lo, hi]
 };
 
 static std::vector<TuneEntry> tune_table() {
@@ -132,8 +132,8 @@ static std::vector<TuneEntry> tune_table() {
   return {
       {"family", &t.family, 0, 1, false},
       {"rss_k_small", &t.rss_k[0], 4, 16, true},
-      {"rss_k_mid", &t.rss_k[1], 4, 16, true},
-      {"rss_k_large", &t.rss_k[2], 4, 16, true},
+      {"rss_k_mid", &t.rss_k[1], 4, 32, true},
+      {"rss_k_large", &t.rss_k[2], 4, 64, true},
       {"persist_occ", &t.persist_occ, 0, 16, false},
       {"rss_rounds", &t.rss_rounds, 1, 64, false},
       {"interleave", &t.interleave, 0, 1, false},
@@ -149,7 +149,7 @@ static ss_status set_tuning(const char* name, int64_t value) {
   for (const TuneEntry& e : tune_table()) {
     if (std::strcmp(e.name, name) != 0) continue;
     if (value < e.lo || value > e.hi) return SS_EINVAL;
-    if (e.pow2_k && value != 4 && value != 8 && value != 16) return SS_EINVAL;
+    if (e.pow2_k && (value & (value - 1)) != 0) return SS_EINVAL;
     *e.slot = (int)value;
     return SS_OK;
   }

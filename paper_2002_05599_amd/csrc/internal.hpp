@@ -9,7 +9,7 @@ namespace ss {
 // Variant choices, set by the autotuner through ss_set_tuning_value.
 struct Tuning {
   int family = 0;        // network family for n <= 16 (0 fewest comparators, 1 Bose-Nelson)
-  int rss_k[3] = {4, 8, 16};  // level-0 bucket count for 17..64, 65..128, 129..256 keys
+  int rss_k[3] = {16, 32, 64};  // level-0 bucket count for 17..64, 65..128, 129..256 keys
   int persist_occ = 0;   // work-groups per CU for the persistent grid (0 = occupancy limit)
   int rss_rounds = 16;    // rounds of groups per RSS tile in the segmented kernels
   int interleave = 1;    // persistent kernel alternates RSS and network tiles

@@ -15,7 +15,7 @@ __global__ void __launch_bounds__(kRssThreads)
 rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip, int k0) {
   constexpr int kGroups = kWave / G;
   __shared__ GroupLds<K, false, G> lds[kRssWaves * kGroups];
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
   const int g = lane_id() / G;
   const int64_t arr = ((int64_t)blockIdx.x * kRssWaves + wave) * kGroups + g;
   const int m = arr < count ? n : 0;

@@ -57,9 +57,13 @@ template <class K, bool V, int G> struct GroupLds {
   static constexpr int kPad = 17;
   K key[kCap + kPad];
   uint32_t val[V ? kCap + kPad : 1];
-  K sample[kMaxPend][16];          // sorted sample of each pending bucket
-  uint32_t cnt[kMaxPend][16];      // per (bucket, child): count, then child offset
-  uint8_t nextpb[kMaxPend][16];    // pending index of each child at the next level, or 0xFF
+  // Per pending bucket b, 16 entries from b*16: its sorted sample, the count
+  // (then offset) of each child and each child's pending index at the next
+  // level (0xFF if none).  The first level has one bucket and may use up to
+  // 64 entries (k = 32 or 64 children), which the arrays hold for G >= 32.
+  K sample[kMaxPend * 16];
+  uint32_t cnt[kMaxPend * 16];
+  uint8_t nextpb[kMaxPend * 16];
   uint8_t deg[kMaxPend];           // all splitters of the bucket equal
   uint8_t pb[kCap];                // pending bucket of each position, or 0xFF
   uint16_t pend_st[2][kMaxPend];
@@ -164,51 +168,110 @@ __device__ __forceinline__ void finish_dispatch(GroupLds<K, V, G>& L, bool ok, i
 // Oversampling factor a for k buckets: the sample of a*k keys must fit one
 // network of at most 16 channels.  k = 4 uses a = 3 (12 samples), the
 // parameters the paper found best on most machines ("332", Section 4.5).
-__host__ __device__ constexpr int oversampling(int k) { return k == 4 ? 3 : 16 / k; }
+__host__ __device__ constexpr int oversampling(int k) { return k == 4 ? 3 : (k >= 16 ? 1 : 16 / k); }
+
+// Largest first-level bucket count a G-lane group supports: the first
+// level's children are scanned in one pass of the group's lanes, and their
+// per-bucket entries must fit the arrays above.
+__host__ __device__ constexpr int max_first_k(int G) { return G >= 64 ? 64 : (G >= 32 ? 32 : 16); }
+
+// x of lane (lane ^ J), for a compile-time J: DPP for the quad and row
+// patterns, a ds_swizzle within 32 lanes otherwise, a lane permute only when
+// the partner is in the other half of the wave.  None needs an address
+// register.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t x) {
+  const int v = (int)x;
+  if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);  // quad [1,0,3,2]
+  else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // [2,3,0,1]
+  else if constexpr (J == 3) return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x1B, 0xF, 0xF, true);  // [3,2,1,0]
+  else if constexpr (J == 7) return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // half-row mirror
+  else if constexpr (J == 15) return (uint32_t)__builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, true);  // row mirror
+  else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x1F | (J << 10));  // bitmask mode
+  else return read_lane(x, lane_id() ^ J);
+}
+
+template <int J, class K>
+__device__ __forceinline__ K lane_xor_key(K x) {
+  if constexpr (sizeof(K) == 8)
+    return ((K)lane_xor<J>((uint32_t)(x >> 32)) << 32) | lane_xor<J>((uint32_t)x);
+  else
+    return lane_xor<J>(x);
+}
+
+// Compare-exchange with the lane J apart: the lane whose bit B is clear keeps
+// the minimum, the other the maximum.
+template <int J, int B, class K>
+__device__ __forceinline__ K team_exchange(K x, int t) {
+  const K y = lane_xor_key<J>(x);
+  const bool lower = (t & B) == 0;
+  return lower ? (y < x ? y : x) : (y < x ? x : y);
+}
+
+template <int KBLK, int J, class K>
+__device__ __forceinline__ K team_half_cleaners(K x, int t) {
+  if constexpr (J >= 1) {
+    x = team_exchange<J, J>(x, t);
+    return team_half_cleaners<KBLK, J / 2>(x, t);
+  } else {
+    return x;
+  }
+}
+
+template <int KBLK, int T, class K>
+__device__ __forceinline__ K team_merges(K x, int t) {
+  if constexpr (KBLK <= T) {
+    x = team_exchange<KBLK - 1, KBLK / 2>(x, t);
+    x = team_half_cleaners<KBLK, KBLK / 4>(x, t);
+    return team_merges<KBLK * 2, T>(x, t);
+  } else {
+    return x;
+  }
+}
+
+// Sorts x ascending across each aligned team of T lanes (T a power of two)
+// with Batcher's bitonic network in its one-direction form: each merge of
+// blocks of size k starts by comparing lane i with its mirror i ^ (k-1) and
+// continues with the half-cleaners i ^ j (j = k/4, ..., 1); in every exchange
+// the lower lane keeps the minimum.  log T (log T + 1) / 2 exchange stages.
+// t = lane index within the team.
+template <int T, class K>
+__device__ __forceinline__ K team_sort(K x, int t) {
+  return team_merges<2, T>(x, t);
+}
 
 // Sample of NS = a*k keys (k = KB buckets) at positions
-// floor((2t+1)*size/(2*NS)) of each pending bucket (a team of NS lanes per
-// bucket, one key per lane), sorted by rank within the team; also clears the
-// bucket's child counters and records whether all of its k-1 splitters are
-// equal.
+// floor((2t+1)*size/(2*NS)) of each pending bucket (a team of T >= NS lanes
+// per bucket, one key per lane, the T - NS spare lanes holding the maximum
+// key), sorted across the team; also clears the bucket's child counters and
+// records whether all of its k-1 splitters are equal.
 template <int KB, class K, bool V, int G>
 __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
   constexpr int A = oversampling(KB);
   constexpr int NS = A * KB;
-  constexpr int PER = G / NS;  // buckets sampled per pass (one NS-lane team each)
+  constexpr int T = NS <= 16 ? 16 : NS;   // team size, a power of two
+  constexpr int PER = G / T;              // buckets sampled per pass
+  constexpr int kSpan = KB > 16 ? KB : 16;
+  static_assert(PER >= 1 && T * PER == G, "team must divide the group");
   const int lane = lane_id();
   const int gl = lane % G;
-  const int team = gl / NS;
-  const int t = gl - team * NS;
-  const int team_base = lane - t;
+  const int team = gl / T;
+  const int t = gl - team * T;
   for (int b0 = 0; ballot(b0 < np) != 0ull; b0 += PER) {
     const int b = b0 + team;
-    const bool own = team < PER && b < np;
+    const bool own = b < np;
     const int st = own ? (int)L.pend_st[cur][b] : 0;
     const int sz = own ? (int)L.pend_sz[cur][b] : 0;
-    const K x = own ? L.key[st + ((2 * t + 1) * sz) / (2 * NS)] : K(0);
-    // rank of x in the team's sample: smaller keys, plus equal keys of lower lanes
-    int rank = 0;
-#pragma unroll 1
-    for (int u = 0; u < NS; ++u) {
-      K y;
-      if constexpr (sizeof(K) == 8) {
-        const uint32_t lo = read_lane((uint32_t)x, team_base + u);
-        const uint32_t hi = read_lane((uint32_t)(x >> 32), team_base + u);
-        y = ((K)hi << 32) | lo;
-      } else {
-        y = read_lane(x, team_base + u);
-      }
-      rank += (y < x || (y == x && u < t)) ? 1 : 0;
-    }
+    K x = KeyTraits<K>::kMax;
+    if (own && t < NS) x = L.key[st + ((2 * t + 1) * sz) / (2 * NS)];
+    x = team_sort<T>(x, t);
     if (own) {
-      L.sample[b][rank] = x;
-      L.cnt[b][t] = 0;
-      if (t < 16 - NS) L.cnt[b][NS + t] = 0;
+      if (t < NS) L.sample[b * 16 + t] = x;
+      if (t < kSpan) L.cnt[b * kSpan + t] = 0;
     }
     wave_lds_sync();
     // all k-1 splitters equal: the smallest (rank A) equals the largest (rank A*(k-1))
-    if (own && t == 0) L.deg[b] = L.sample[b][A - 1] == L.sample[b][A * (KB - 1) - 1] ? 1 : 0;
+    if (own && t == 0) L.deg[b] = L.sample[b * 16 + A - 1] == L.sample[b * 16 + A * (KB - 1) - 1] ? 1 : 0;
   }
 }
 
@@ -249,6 +312,9 @@ template <int LOGK, bool kFirst, class K, bool V, int G>
 __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
   constexpr int k = 1 << LOGK;
   constexpr int a = oversampling(k);
+  constexpr int kSpan = k > 16 ? k : 16;  // entries per bucket in cnt/nextpb
+  static_assert(kFirst || k <= 16, "only the first level has more than 16 children");
+  static_assert(kSpan <= G, "the children of a bucket are scanned in one pass");
   const int lane = lane_id();
   const int gl = lane % G;
   const int gbase = lane - gl;
@@ -263,65 +329,62 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
   bool deg0 = false;
   if constexpr (kRegTree) {
 #pragma unroll
-    for (int i = 0; i < k - 1; ++i) spl[i] = np > 0 ? L.sample[0][a * (i + 1) - 1] : K(0);
+    for (int i = 0; i < k - 1; ++i) spl[i] = np > 0 ? L.sample[a * (i + 1) - 1] : K(0);
     deg0 = np > 0 && spl[0] == spl[k - 2];
   } else if constexpr (kFirst) {
     deg0 = np > 0 && L.deg[0] != 0;
   }
 
+  // per slot: the key, its payload and where it goes -- the index of its
+  // (bucket, child) entry << 16 | its rank among that child's keys, or ~0 if
+  // the key is not in a pending bucket
   K e[4];
   uint32_t v[4];
-  int c[4], pbk[4];
-  uint32_t rk[4];
-  bool ok[4];
+  uint32_t dst[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int i = gl + G * s;
-    ok[s] = false;
-    c[s] = 0;
-    pbk[s] = 0;
-    rk[s] = 0;
+    dst[s] = ~0u;
     if (ballot(i < m) == 0ull) continue;  // no group has keys in this slot
     int pp = 0xFF;
     if (i < m) pp = kFirst ? (np > 0 ? 0 : 0xFF) : (int)L.pb[i];
-    ok[s] = pp != 0xFF;
-    e[s] = ok[s] ? L.key[i] : K(0);
-    if constexpr (V) v[s] = ok[s] ? L.val[i] : 0u;
+    const bool ok = pp != 0xFF;
+    e[s] = ok ? L.key[i] : K(0);
+    if constexpr (V) v[s] = ok ? L.val[i] : 0u;
     int cc;
     if constexpr (kRegTree) {
       cc = classify<LOGK>(e[s], spl);
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], spl[0]);
     } else if constexpr (kFirst) {
-      const K* smp = L.sample[0];
+      const K* smp = &L.sample[0];
       cc = lds_bucket<LOGK, a>(e[s], smp);
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], smp[a - 1]);
     } else {
-      const int q = ok[s] ? pp : 0;
-      const K* smp = L.sample[q];
+      const int q = ok ? pp : 0;
+      const K* smp = &L.sample[q * 16];
       cc = lds_bucket<LOGK, a>(e[s], smp);
       const bool dg = L.deg[q] != 0;
       if (ballot(dg) != 0ull && dg) cc = three_way(e[s], smp[a - 1]);
     }
-    c[s] = cc;
-    pbk[s] = pp;
     // rank among the keys of the same (bucket, child): an LDS atomic counter
-    rk[s] = ok[s] ? atomicAdd(&L.cnt[pp][cc], 1u) : 0u;
+    const int ci = pp * kSpan + cc;
+    if (ok) dst[s] = ((uint32_t)ci << 16) | atomicAdd(&L.cnt[ci], 1u);
   }
   wave_lds_sync();
 
   // scan each bucket's child counts into offsets; register the children
-  for (int r0 = 0; ballot(r0 < np * 16) != 0ull; r0 += G) {
+  for (int r0 = 0; ballot(r0 < np * kSpan) != 0ull; r0 += G) {
     const int q = r0 + gl;
-    const int pq = q >> 4;
-    const int cq = q & 15;
+    const int pq = q / kSpan;
+    const int cq = q % kSpan;
     const bool okq = pq < np;
     const bool dg = okq && L.deg[pq] != 0;
     const int nchq = okq ? (dg ? 3 : k) : 0;
     const bool own = cq < nchq;
-    const uint32_t x = own ? L.cnt[pq][cq] : 0u;
+    const uint32_t x = own ? L.cnt[q] : 0u;
     uint32_t incl = x;
 #pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
+    for (int d = 1; d < kSpan; d <<= 1) {
       const uint32_t y = read_lane(incl, cq >= d ? lane - d : lane);
       if (cq >= d) incl += y;
     }
@@ -333,7 +396,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     const bool is_pend = own && !eq && csz > 16;
     const uint64_t Fm = ballot(is_fin) & gmask;
     const uint64_t Pm = ballot(is_pend) & gmask;
-    if (own) L.cnt[pq][cq] = off;
+    if (own) L.cnt[q] = off;
     if (is_fin) {
       const int idx = min(nf + (int)__popcll(Fm & below), GroupLds<K, V, G>::kMaxFin - 1);
       L.fin[idx] = fin_pack(cst, csz);
@@ -344,7 +407,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
       L.pend_st[cur ^ 1][pidx] = (uint16_t)cst;
       L.pend_sz[cur ^ 1][pidx] = (uint16_t)csz;
     }
-    if (own) L.nextpb[pq][cq] = (uint8_t)pidx;
+    if (own) L.nextpb[q] = (uint8_t)pidx;
     // The list sizes are bounded by the array size (disjoint buckets of at
     // least 2, resp. 17, keys); the clamps only keep every loop bounded.
     nf = min(nf + (int)__popcll(Fm), GroupLds<K, V, G>::kMaxFin);
@@ -355,11 +418,12 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
   // scatter in place (every key of the slots was read above)
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    if (ok[s]) {
-      const int pos = (int)L.pend_st[cur][pbk[s]] + (int)L.cnt[pbk[s]][c[s]] + (int)rk[s];
+    if (dst[s] != ~0u) {
+      const int pc = (int)(dst[s] >> 16);
+      const int pos = (int)L.pend_st[cur][pc / kSpan] + (int)L.cnt[pc] + (int)(dst[s] & 0xFFFFu);
       L.key[pos] = e[s];
       if constexpr (V) L.val[pos] = v[s];
-      L.pb[pos] = L.nextpb[pbk[s]][c[s]];
+      L.pb[pos] = L.nextpb[pc];
     }
   }
   wave_lds_sync();
@@ -430,23 +494,35 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
       rank_sort_pending(L, cur, np);
       break;
     }
-    const int kk = level == 0 ? k0 : 4;
-    if (kk == 16)
-      sample_phase<16>(L, cur, np);
-    else if (kk == 8)
-      sample_phase<8>(L, cur, np);
-    else
-      sample_phase<4>(L, cur, np);
-    wave_lds_sync();
+    const int kk = level == 0 ? min(k0, max_first_k(G)) : 4;
     int npn = 0;
-    if (level == 0) {
-      if (kk == 16)
-        split_level<4, true>(L, m, cur, np, nf, npn);
-      else if (kk == 8)
-        split_level<3, true>(L, m, cur, np, nf, npn);
-      else
-        split_level<2, true>(L, m, cur, np, nf, npn);
+    if (kk == 64) {
+      if constexpr (max_first_k(G) >= 64) {
+        sample_phase<64>(L, cur, np);
+        wave_lds_sync();
+        split_level<6, true>(L, m, cur, np, nf, npn);
+      }
+    } else if (kk == 32) {
+      if constexpr (max_first_k(G) >= 32) {
+        sample_phase<32>(L, cur, np);
+        wave_lds_sync();
+        split_level<5, true>(L, m, cur, np, nf, npn);
+      }
+    } else if (kk == 16) {
+      sample_phase<16>(L, cur, np);
+      wave_lds_sync();
+      split_level<4, true>(L, m, cur, np, nf, npn);
+    } else if (kk == 8) {
+      sample_phase<8>(L, cur, np);
+      wave_lds_sync();
+      split_level<3, true>(L, m, cur, np, nf, npn);
+    } else if (level == 0) {
+      sample_phase<4>(L, cur, np);
+      wave_lds_sync();
+      split_level<2, true>(L, m, cur, np, nf, npn);
     } else {
+      sample_phase<4>(L, cur, np);
+      wave_lds_sync();
       split_level<2, false>(L, m, cur, np, nf, npn);
     }
     np = npn;

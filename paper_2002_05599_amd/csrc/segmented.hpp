@@ -295,12 +295,15 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
 // The kernel holding every handler would otherwise take more registers than
 // the largest of them and lose the occupancy that the latency-bound RSS
 // tiles need; the single-kind kernels keep their natural register count.
+// Register budget of the persistent kernels, as resident waves per SIMD
+// (VGPRs <= 512 / waves): the most each kind reaches without spilling.
 template <class K, bool V, int KS> struct PersistWaves {
-  static constexpr int value = KS == kKindAll ? (sizeof(K) == 4 ? (V ? 4 : 5) : (V ? 3 : 4))
+  static constexpr int kType = (sizeof(K) == 8 ? 2 : 0) + (V ? 1 : 0);  // u32, u32+v, u64, u64+v
+  static constexpr int value = KS == kKindAll   ? (kType == 0 ? 5 : (kType == 3 ? 3 : 4))
                                : KS == kKindNet ? 1
-                               : (sizeof(K) == 4 && !V) ? 6
-                               : sizeof(K) == 4          ? 5
-                                                         : 4;
+                               : kType == 0     ? 6
+                               : (kType == 1 && KS == kKindRss16) ? 5
+                                                                  : 4;
 };
 
 template <class K, bool V, int KS> struct PersistLds {
@@ -317,22 +320,59 @@ template <int F, class K, bool V, int KS>
 __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(PersistWaves<K, V, KS>::value)))
 seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][PersistLds<K, V, KS>::kBytes];
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
   const int waves = (int)gridDim.x * kSortWaves;
+  // Work is split into kTileParts partitions, partition p = blockIdx mod 8
+  // (on one XCD), each with its own claim counter on its own cache line.
+  const int part = (int)blockIdx.x % kTileParts;
+  const int part_blocks = ((int)gridDim.x - part + kTileParts - 1) / kTileParts;
+  const int part_waves = part_blocks * kSortWaves;
+  const int wi = ((int)blockIdx.x / kTileParts) * kSortWaves + wave;  // wave index within the partition
+  uint32_t* counter = &ctrl[kCtrlTile + (KS * kTileParts + part) * 32];
+
   constexpr bool kSingle = KS >= kKindRss16;
-  constexpr int kFixedClass = kSingle ? kNetClasses + (KS - kKindRss16) : 0;
+  if constexpr (kSingle) {
+    // One RSS class, in units of one round (one array per lane group).
+    // Partition p owns a contiguous range of units; its waves take chunks of
+    // `rounds` units round-robin, and the last part -- about one chunk per
+    // wave -- in pieces of a quarter chunk claimed from the partition's
+    // counter, so the waves finish within about a quarter chunk of each
+    // other.
+    constexpr int kClass = kNetClasses + (KS - kKindRss16);
+    constexpr int G = KS == kKindRss16 ? 16 : (KS == kKindRss32 ? 32 : 64);
+    constexpr int kGroups = kWave / G;
+    const int count = (int)a.ctrl[kCtrlCount + kClass];
+    const int list = (int)a.ctrl[kCtrlStart + kClass];
+    const int k0 = a.k0[KS - kKindRss16];
+    auto run_units = [&](int u, int n) {
+      rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0);
+    };
+    const int units = (count + kGroups - 1) / kGroups;
+    const int R = class_rounds(kClass, count, a.rounds, waves, kPersistTpw);
+    const int u0 = (int)((int64_t)units * part / kTileParts);
+    const int u1 = (int)((int64_t)units * (part + 1) / kTileParts);
+    const int static_chunks = max(0, (u1 - u0) / R - part_waves);
+    for (int q = wi; q < static_chunks; q += part_waves) run_units(u0 + q * R, R);
+    const int d0 = u0 + static_chunks * R;
+    const int piece = max(1, R / 4);
+    if (d0 >= u1) return;
+    while (true) {
+      int c0 = 0;
+      if (lane_id() == 0) c0 = (int)atomicAdd(counter, 1u);
+      const int u = d0 + __builtin_amdgcn_readfirstlane(c0) * piece;
+      if (u >= u1) break;
+      run_units(u, min(piece, u1 - u));
+    }
+    return;
+  }
   // tiles of the RSS classes and of the network classes (wave-uniform)
   int t_rss = 0, t_net = 0;
-  if constexpr (kSingle) {
-    t_rss = class_tiles<KS>(a.ctrl, kFixedClass, a.rounds, waves);
-  } else {
-    for (int c = 0; c < kClasses; ++c) {
-      const int n = class_tiles<KS>(a.ctrl, c, a.rounds, waves);
-      if (c >= kNetClasses)
-        t_rss += n;
-      else
-        t_net += n;
-    }
+  for (int c = 0; c < kClasses; ++c) {
+    const int n = class_tiles<KS>(a.ctrl, c, a.rounds, waves);
+    if (c >= kNetClasses)
+      t_rss += n;
+    else
+      t_net += n;
   }
   // the network-only kernel keeps its class prefix in registers
   int net_first[kNetClasses + 1];
@@ -346,17 +386,13 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
     net_first[kNetClasses] = acc;
   }
   const int total = t_rss + t_net;
-  const int fixed_count = kSingle ? (int)a.ctrl[kCtrlCount + kFixedClass] : 0;
-  const int fixed_list = kSingle ? (int)a.ctrl[kCtrlStart + kFixedClass] : 0;
   // Tiles are handed out round-robin by wave index, except the last ones
-  // (two per wave), which waves claim from an atomic counter as they finish so
-  // that uneven tiles do not leave a tail.  (Claiming every tile atomically
-  // costs more: the counter is shared by all XCDs.)
+  // (half a tile per wave), which waves claim from their partition's counter
+  // as they finish so that uneven tiles do not leave a tail.  (Claiming every
+  // tile from one device-wide counter costs more: atomics on one line from all
+  // XCDs serialise.)
   auto process = [&](int t) {
-    if constexpr (kSingle) {
-      run_tile<F, K, V, KS>(lds[wave], keys, vals, a, flip, kFixedClass, t, fixed_count, fixed_list,
-                            waves);
-    } else if constexpr (KS == kKindNet) {
+    if constexpr (KS == kKindNet) {
       int c = 0, idx = 0;
 #pragma unroll
       for (int o = 0; o < kNetClasses; ++o) {
@@ -374,16 +410,9 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
                             (int)a.ctrl[kCtrlStart + c], waves);
     }
   };
-  // Tiles t = part + 8*i belong to partition part = blockIdx % 8; within a
-  // partition the waves take tiles round-robin, and the last ones (half a
-  // tile per wave) are claimed from the partition's own counter.
-  const int part = (int)blockIdx.x % kTileParts;
-  const int part_blocks = ((int)gridDim.x - part + kTileParts - 1) / kTileParts;
-  const int part_waves = part_blocks * kSortWaves;
-  const int wi = ((int)blockIdx.x / kTileParts) * kSortWaves + wave;
+  // Tiles t = part + 8*i belong to partition part.
   const int part_tiles = (total - part + kTileParts - 1) / kTileParts;
   const int static_end = part_tiles - min(part_tiles, part_waves / 2);
-  uint32_t* counter = &ctrl[kCtrlTile + (KS * kTileParts + part) * 32];
   int i = wi;
   while (true) {
     if (i >= static_end) {  // dynamic tail: claim the next tile of the partition
@@ -408,7 +437,7 @@ __global__ void __launch_bounds__(kSortThreads)
 seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, K flip, int c, int count,
                  int list) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][KIND == 0 ? 16 : WaveLds<K, V>::kBytes];
-  const int wave = threadIdx.x / kWave;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
   const int tile = blockIdx.x * kSortWaves + wave;
   const int rounds = class_rounds(c, count, a.rounds, a.waves, kPlainTpw);
   const int first = tile * class_tile(c, rounds);
@@ -464,7 +493,8 @@ static int persistent_blocks(DeviceCtx* c) {
       nb = 2;
     occ = nb;
   }
-  return occ * c->num_cus;
+  // every partition (blockIdx mod kTileParts) needs at least one work-group
+  return max(occ * c->num_cus, kTileParts);
 }
 
 inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {

@@ -75,6 +75,17 @@ def test_tuning_roundtrip(lib, tmp_path):
     with pytest.raises(ss.SmallSortError):
         ss.set_tuning("rss_k_small", 5)
     with pytest.raises(ss.SmallSortError):
+        ss.set_tuning("rss_k_small", 32)  # a 16-lane group takes at most 16 buckets
+    old_mid, old_large = ss.get_tuning("rss_k_mid"), ss.get_tuning("rss_k_large")
+    ss.set_tuning("rss_k_mid", 32)
+    ss.set_tuning("rss_k_large", 64)
+    assert ss.get_tuning("rss_k_mid") == 32 and ss.get_tuning("rss_k_large") == 64
+    for name, bad in (("rss_k_mid", 64), ("rss_k_large", 48), ("rss_k_large", 128), ("rss_k_large", 2)):
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning(name, bad)
+    ss.set_tuning("rss_k_mid", old_mid)
+    ss.set_tuning("rss_k_large", old_large)
+    with pytest.raises(ss.SmallSortError):
         ss.set_tuning("no_such_knob", 1)
     assert ss.get_tuning("no_such_knob") == -1
     f = tmp_path / "t.json"

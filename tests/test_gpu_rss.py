@@ -84,17 +84,29 @@ def test_rss_every_size_u32():
         assert (got == want).all(), f"n={n}: {first_mismatch(got, want, n)}"
 
 
-@pytest.mark.parametrize("tuning", [("rss_k_small", 16), ("rss_k_mid", 4), ("rss_k_large", 4),
-                                    ("rss_k_large", 8), ("family", 1)])
+TUNINGS = [("rss_k_small", 4), ("rss_k_small", 8), ("rss_k_small", 16),
+           ("rss_k_mid", 4), ("rss_k_mid", 8), ("rss_k_mid", 16), ("rss_k_mid", 32),
+           ("rss_k_large", 4), ("rss_k_large", 8), ("rss_k_large", 16), ("rss_k_large", 32),
+           ("rss_k_large", 64), ("family", 0), ("family", 1)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t[0]}={t[1]}")
 def test_rss_tuning_variants(tuning):
+    """Every first-level bucket count and family: uniform keys of every class,
+    duplicate-heavy keys (three-way splits) and 64-bit keys."""
     name, value = tuning
     old = ss.get_tuning(name)
     ss.set_tuning(name, value)
     try:
-        for n in (20, 64, 100, 256):
+        for n in (20, 64, 65, 100, 128, 129, 200, 256):
             a = inputs.random_keys(np.int32, n * 50, seed=n)
             got = run_fixed(a, n, 50, n)
             assert (got == oracle.sort_fixed(a, n, 50, n)).all(), (name, value, n)
+            for kind in ("zipf", "two_values", "one_big_dup", "max_heavy"):
+                a = special(np.uint64, n, 21, kind, seed=n + 1)
+                got = run_fixed(a, n, 21, n)
+                want = oracle.sort_fixed(a, n, 21, n)
+                assert (got == want).all(), (name, value, n, kind, first_mismatch(got, want, n))
     finally:
         ss.set_tuning(name, old)
 

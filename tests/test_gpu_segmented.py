@@ -186,3 +186,33 @@ def test_config4_full_size_sampled():
     # payload is the in-segment index: it must index the original segment
     seg_start = np.repeat(off[:-1], np.diff(off)).astype(np.int64)
     assert (keys[seg_start + gv.astype(np.int64)] == gk).all()
+
+
+@pytest.mark.parametrize("k", [4, 8, 16, 32, 64])
+@pytest.mark.parametrize("mode", [ss.MODE_AUTO, ss.MODE_PLAIN], ids=["graph", "plain"])
+def test_first_level_bucket_counts_with_payload(k, mode):
+    """Every first-level bucket count on the RSS classes, distinct 64-bit keys
+    with payload (exact) and duplicate-heavy 32-bit keys (keys exact)."""
+    names = ("rss_k_small", "rss_k_mid", "rss_k_large")
+    caps = (16, 32, 64)
+    old = [ss.get_tuning(n) for n in names]
+    try:
+        for n, cap in zip(names, caps):
+            ss.set_tuning(n, min(k, cap))
+        sizes = np.random.default_rng(k).integers(17, 257, size=3000)
+        off = inputs.offsets_from_sizes(sizes)
+        total = int(off[-1])
+        keys = inputs.distinct_u64(total, seed=k)
+        vals = inputs.segment_index_payload(off)
+        gk, gv = run_seg(keys, off, vals, mode=mode)
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (gk == wk).all(), first_mismatch(gk, wk)
+        assert (gv == wv).all(), first_mismatch(gv, wv)
+        dup = (inputs.random_keys(np.uint32, total, seed=k) % 5).astype(np.uint32)
+        gk, _ = run_seg(dup, off, mode=mode)
+        wk, _ = oracle.sort_segments(dup, off)
+        assert (gk == wk).all(), first_mismatch(gk, wk)
+        assert ss.device_status() == 0
+    finally:
+        for n, v in zip(names, old):
+            ss.set_tuning(n, v)
