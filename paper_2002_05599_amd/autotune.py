@@ -137,7 +137,7 @@ SPACE = [
     ("rss_k_small", [4, 8, 16], "rss"),
     ("rss_k_mid", [4, 8, 16, 32], "rss"),
     ("rss_k_large", [4, 8, 16, 32, 64], "rss"),
-    ("rss_rounds", [4, 8, 16, 32], "ragged"),
+    ("rss_rounds", [4, 8, 16, 32, 64], "ragged"),
     ("persist_split", [0, 1], "ragged"),
     ("interleave", [0, 1], "ragged"),
     ("persist_occ", [0, 1, 2, 3], "ragged"),
