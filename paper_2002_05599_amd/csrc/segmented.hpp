@@ -164,8 +164,9 @@ template <class K, bool V> struct WaveLds {
 
 // One tile: `rounds` rounds of kWave/G arrays (one per G-lane group).  The
 // segment bounds of up to 64 arrays are fetched at once (one per lane) and
-// handed to the groups with lane permutes, so a round waits for global memory
-// once (its keys) instead of three times (id, bounds, keys).
+// handed to the groups with lane permutes, and the next round's keys are
+// loaded into registers before the current round is sorted, so the sort
+// hides the load latency.
 template <int F, class K, bool V, int G>
 __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint32_t* vals,
                                          const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
@@ -176,7 +177,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
   const int g = lane / G;
   const int narr = rounds * kGroups;
   int meta_lo = 0, meta_m = 0;  // lane l: bounds of array a0 + l of the tile
-  for (int r = 0; r < rounds; ++r) {
+  auto bounds = [&](int r, int& lo, int& m) {
     const int a0 = r * kGroups;
     if ((a0 & (kWave - 1)) == 0) {
       const int a = a0 + lane;
@@ -190,9 +191,45 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
       }
     }
     const int src = (a0 & (kWave - 1)) + g;
-    const int lo = (int)read_lane((uint32_t)meta_lo, src);
-    const int m = (int)read_lane((uint32_t)meta_m, src);
-    rss_group_sort<F, K, V, G>(L[g], keys + lo, V ? vals + lo : nullptr, m, flip, k0);
+    lo = (int)read_lane((uint32_t)meta_lo, src);
+    m = (int)read_lane((uint32_t)meta_m, src);
+  };
+  const int gl = lane % G;
+  K nk[4];
+  uint32_t nv[4];
+  auto fetch = [&](int lo, int m) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = gl + G * s;
+      if (i < m) {
+        nk[s] = keys[lo + i];
+        if constexpr (V) nv[s] = vals[lo + i];
+      }
+    }
+  };
+  int lo, m;
+  bounds(0, lo, m);
+  fetch(lo, m);
+  for (int r = 0; r < rounds; ++r) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = gl + G * s;
+      if (i < m) {
+        L[g].key[i] = nk[s] ^ flip;
+        if constexpr (V) L[g].val[i] = nv[s];
+      }
+    }
+    wave_lds_sync();
+    int lo_n = 0, m_n = 0;
+    if (r + 1 < rounds) {
+      bounds(r + 1, lo_n, m_n);
+      fetch(lo_n, m_n);
+    }
+    rss_group_sort_lds<F>(L[g], m, k0);
+    rss_group_store(L[g], keys + lo, V ? vals + lo : nullptr, m, flip);
+    wave_lds_sync();
+    lo = lo_n;
+    m = m_n;
   }
 }
 
