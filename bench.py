@@ -68,14 +68,15 @@ def kernel_source_hash(kernel_key):
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_key):
-    """HBM bytes per launch from profiles/traffic.json, if the kernels are unchanged."""
+def traffic_for(kernel_key, family):
+    """HBM bytes per launch from profiles/traffic.json, if the counters were taken
+    on the same kernel: unchanged sources and the same network family."""
     try:
         data = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     except (OSError, ValueError):
         return None
     ent = data.get(kernel_key)
-    if not ent or ent.get("source_hash") != kernel_source_hash(kernel_key):
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel_key) or ent.get("family") != family:
         return None
     return ent.get("bytes_per_launch")
 
@@ -156,6 +157,7 @@ def bench_fixed16(args):
     algo_bytes = 2 * nkeys * 4
     achieved = algo_bytes / (ms * 1e-3) / 1e9
     kkey = "fixed_tile_kernel<n=16,u32>"
+    family = ss.get_tuning("family")
     del bufs, keys
     torch.cuda.empty_cache()
     return {
@@ -166,8 +168,8 @@ def bench_fixed16(args):
         "config": {"workload": f"batched network sort, 2^{count_log2} arrays x n={n} uint32, uniform, "
                                f"stride {n}", "n": n, "count": count, "key": "uint32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(kkey),
-                     "kernel": kkey, "algorithmic_bytes_per_launch": algo_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(kkey, family),
+                     "kernel": kkey, "network_family": family, "algorithmic_bytes_per_launch": algo_bytes},
     }
 
 
