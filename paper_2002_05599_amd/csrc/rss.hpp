@@ -4,13 +4,14 @@
 // The array is staged in LDS.  Each level of the recursion handles every
 // pending bucket (more than 16 keys) of the array:
 //
-//   1. sample: a team of a*k lanes per pending bucket picks a*k keys at
+//   1. sample: a team of lanes per pending bucket picks a*k keys at
 //      equidistant positions floor((2t+1)*size/(2ak)), one per lane, and
-//      sorts them by rank (each lane counts the team's keys that precede its
-//      own, ties broken by lane); the paper sorts the sample with its
-//      base-case sorter (Section 3) -- any sort gives the same sorted sample.
-//      k buckets with oversampling a = 3 for k = 4 (the paper's "332"),
-//      a = 16/k for k = 8 and 16;
+//      sorts them with a bitonic network laid across the team's lanes (the
+//      paper sorts the sample with its base-case sorting network, Section 3;
+//      here the network spans lanes instead of one lane's registers).  k
+//      buckets with oversampling a = 3 for k = 4 (the paper's "332"), a = 2
+//      for k = 8 and a = 1 for k = 16, 32, 64 (the first level may use 32 or
+//      64 buckets for arrays of more than 64 or 128 keys; later levels use 4);
 //   2. splitters: s_i = S_{a*i} for i = 1..k-1 (Section 3, basic sample
 //      sort);
 //   3. classify: bucket j = #{splitters < e}, i.e. s_j < e <= s_{j+1}, found
@@ -18,7 +19,10 @@
 //      the root, then keep either the left or the right subtree with selects
 //      (the paper's "unconditional copy of the left subtree, conditionally
 //      overwritten with the right one"), and append the comparison bit to the
-//      bucket index, j = 2j + [e > root];
+//      bucket index, j = 2j + [e > root].  The first level holds a narrow
+//      tree (at most 32 bytes of splitters) in registers; wider trees and
+//      later levels, whose lanes work on different buckets, search the
+//      bucket's sorted sample in LDS with the same branch-free steps;
 //   4. scatter: a multisplit -- LDS atomic counters give each key its rank
 //      within its bucket, per-bucket counts are scanned into offsets -- and
 //      the keys are written back in bucket order;

@@ -8,28 +8,29 @@
 //
 //   count    each block histograms the size classes of its segments
 //   scan     one block turns the per-block histograms into class totals,
-//            class start offsets and per-block output bases; zeroes the tile
-//            counter
+//            class start offsets and per-block output bases; zeroes the
+//            claim counters
 //   scatter  each block writes its segment ids into the class lists (segment
 //            ids grouped by class; no contended atomics)
-//   sort     one persistent launch: every wave repeatedly claims a tile of
-//            one class (atomic counter, classes ordered from most to least
-//            work per tile) and runs that class's handler:
-//              sizes 2..16: one segment per lane, the network of exactly that
-//                           size in registers;
-//              17..64 / 65..128 / 129..256: Register Sample Sort with 16-,
-//                           32- or 64-lane groups (rss.hpp), several rounds
-//                           of groups per tile.
+//   sort     persistent kernels, by default one per kind: the network
+//            classes (one segment per lane, the network of exactly that size
+//            in registers, 64-segment tiles), then each RSS class (17..64 /
+//            65..128 / 129..256 keys: Register Sample Sort with 16-, 32- or
+//            64-lane groups, rss.hpp).  Work is split into 8 partitions, one
+//            per XCD (blockIdx mod 8), each with its own claim counter; waves
+//            take their share round-robin and claim the remainder in small
+//            pieces at the end, so they finish together.  A single kernel for
+//            every class is kept as a tuning choice.
 //
 // Size classes: 0..14 = sizes 2..16, 15 = 17..64, 16 = 65..128, 17 = 129..256.
 // Sizes 0 and 1 need no work.  A segment longer than 256 keys or with a
 // negative size is skipped and flagged in the status word.
 //
-// Modes: the four kernels replayed from a cached hipGraph (the graph is
-// captured once per key type / payload / network family; each call only
-// rewrites the kernel arguments of its nodes), the same four launched
-// directly, or the "plain" baseline: count/scan/scatter, a copy of the class
-// counts to the host, then one ordinary launch per non-empty class.
+// Modes: the binning and persistent kernels replayed from a cached hipGraph
+// (built once per key type / payload / network family / kernel split; each
+// call only rewrites the kernel arguments of its nodes), the same kernels
+// launched directly, or the "plain" baseline: the binning, a copy of the
+// class counts to the host, then one ordinary launch per non-empty class.
 #pragma once
 
 #include <algorithm>
@@ -280,11 +281,7 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint3
   }
 }
 
-// Position of tile t in class order: returns the class and the tile index
-// within the class.  The hand-out order lists the RSS classes (most work per
-// tile first) and the network classes; with interleaving, RSS and network
-// tiles alternate while both remain, so memory-bound network tiles overlap
-// with ALU/LDS-bound RSS tiles on every CU.
+// Tiles of class c in the kernel of kind set KS (0 if the class is not its).
 template <int KS>
 __device__ __forceinline__ int class_tiles(const uint32_t* ctrl, int c, int rounds, int waves) {
   if (!in_kind(c, KS)) return 0;
@@ -293,6 +290,11 @@ __device__ __forceinline__ int class_tiles(const uint32_t* ctrl, int c, int roun
   return (count + ts - 1) / ts;
 }
 
+// Position of tile t in class order: returns the class and the tile index
+// within the class.  The hand-out order lists the RSS classes (most work per
+// tile first) and the network classes; with interleaving, RSS and network
+// tiles alternate while both remain, so memory-bound network tiles overlap
+// with ALU/LDS-bound RSS tiles on every CU.
 template <int KS>
 __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rounds, int waves, int t_rss,
                                             int t_net, bool interleave, int& cls, int& idx) {
