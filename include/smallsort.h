@@ -137,6 +137,12 @@ const char *ss_strerror(ss_status status);
  *   "persist_split" 1: a persistent kernel for the network classes, then one
  *                  per RSS size class (each with only its own code and
  *                  registers); 0: a single persistent kernel for every class
+ *   "net_mix"      1: in the persistent forms, segments of 2..16 keys are
+ *                  sorted in batch order, 64 per tile of mixed sizes, each
+ *                  lane running the network of the tile's largest segment
+ *                  (neighbouring segments share cache lines); 0: one class
+ *                  per size, each with its exact network.  The plain form
+ *                  always uses one class per size.
  * ss_set_tuning_value returns SS_ENOTUNE for an unknown name, SS_EINVAL for a
  * value out of range.  ss_get_tuning_value returns -1 for an unknown name.
  * ss_load_tuning reads a flat JSON object {"name": integer, ...} with these

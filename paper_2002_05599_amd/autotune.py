@@ -139,6 +139,7 @@ SPACE = [
     ("rss_k_large", [4, 8, 16, 32, 64], "rss"),
     ("rss_rounds", [4, 8, 16, 32, 64], "ragged"),
     ("persist_split", [0, 1], "ragged"),
+    ("net_mix", [0, 1], "ragged"),
     ("interleave", [0, 1], "ragged"),
     ("persist_occ", [0, 1, 2, 3], "ragged"),
 ]

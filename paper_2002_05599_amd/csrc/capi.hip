@@ -138,6 +138,7 @@ static std::vector<TuneEntry> tune_table() {
       {"rss_rounds", &t.rss_rounds, 1, 64, false},
       {"interleave", &t.interleave, 0, 1, false},
       {"persist_split", &t.persist_split, 0, 1, false},
+      {"net_mix", &t.net_mix, 0, 1, false},
   };
 }
 

@@ -14,6 +14,7 @@ struct Tuning {
   int rss_rounds = 16;    // rounds of groups per RSS tile in the segmented kernels
   int interleave = 1;    // persistent kernel alternates RSS and network tiles
   int persist_split = 1;  // 1: one persistent kernel per kind (networks, each RSS class); 0: one for all
+  int net_mix = 0;        // 1: persistent forms sort 2..16-key segments in batch order, mixed sizes
 };
 Tuning& tuning();
 

@@ -56,7 +56,7 @@ constexpr int kCtrlCount = 0;        // [kClasses] segments per class
 constexpr int kCtrlStart = 32;       // [kClasses] start of each class list
 constexpr int kCtrlTile = 128;       // tile counters: kind set k, partition p at kCtrlTile + (8k + p) * 32
 constexpr int kTileParts = 8;        // counter partitions (one 128-byte line each)
-constexpr int kCtrlWords = kCtrlTile + 5 * kTileParts * 32;
+constexpr int kCtrlWords = kCtrlTile + 6 * kTileParts * 32;  // 6 kind sets
 
 __device__ __forceinline__ int size_class(int sz) {
   if (sz < 2) return sz >= 0 ? -1 : -3;  // -1: nothing to do, -3: bad offsets
@@ -98,11 +98,18 @@ __host__ __device__ __forceinline__ int class_at(int order) {
 // --- binning kernels (segmented_common.hip) -----------------------------------
 
 __global__ void seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg,
-                                 uint32_t* __restrict__ blockhist, int* status);
+                                 uint32_t* __restrict__ blockhist, int* status, int mix);
 __global__ void seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restrict__ ctrl);
 __global__ void seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg,
                                    const uint32_t* __restrict__ blockbase, const uint32_t* __restrict__ ctrl,
-                                   int32_t* __restrict__ ids);
+                                   int32_t* __restrict__ ids, int mix);
+
+// Size class used by the binning: with `mix`, every network size goes to
+// class 0, whose segments are then sorted in batch order (see net_tile_mixed).
+__device__ __forceinline__ int bin_class(int sz, int mix) {
+  const int c = size_class(sz);
+  return (mix && c > 0 && c < kNetClasses) ? 0 : c;
+}
 
 // --- tile handlers -----------------------------------------------------------
 
@@ -151,6 +158,69 @@ __device__ __forceinline__ void net_tile_dispatch(int n, K* keys, uint32_t* vals
     case 14: net_tile<F, 14, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
     case 15: net_tile<F, 15, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
     default: net_tile<F, 16, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
+  }
+}
+
+// One segment of n <= N keys in the channels 0..n-1 of an N-key network;
+// channels n.. hold the maximum key, which the strict compare-exchange never
+// moves, so channels 0..n-1 end sorted.
+template <int F, int N, class K, bool V>
+__device__ __forceinline__ void net_sort_padded(K* __restrict__ p, uint32_t* __restrict__ pv, int n, K flip) {
+  K r[N];
+  uint32_t v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = i < n ? (p[i] ^ flip) : KeyTraits<K>::kMax;
+  if constexpr (V) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = i < n ? pv[i] : 0u;
+    net_sort<F, N>(r, v);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (i < n) pv[i] = v[i];
+  } else {
+    net_sort<F, N>(r);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    if (i < n) p[i] = r[i] ^ flip;
+}
+
+// A tile of 64 segments of 2..16 keys of any sizes, in batch order (the
+// class-0 list when the binning mixes the network sizes): one segment per
+// lane, every lane running the network of the wave's largest segment.
+// Segments that are neighbours in memory are then read by the same wave at
+// the same time and share their cache lines, where per-size classes would
+// read each line once per class that touches it.
+template <int F, class K, bool V>
+__device__ __forceinline__ void net_tile_mixed(K* keys, uint32_t* vals, const int32_t* __restrict__ offsets,
+                                               const int32_t* __restrict__ ids, int list, int count, int first,
+                                               K flip) {
+  const int j = first + lane_id();
+  int lo = 0, n = 0;
+  if (j < count) {
+    const int seg = ids[list + j];
+    lo = offsets[seg];
+    n = offsets[seg + 1] - lo;
+  }
+  const int nmax = (int)wave_max((uint32_t)n);
+  K* p = keys + lo;
+  uint32_t* pv = V ? vals + lo : nullptr;
+  switch (nmax) {
+    case 2: net_sort_padded<F, 2, K, V>(p, pv, n, flip); break;
+    case 3: net_sort_padded<F, 3, K, V>(p, pv, n, flip); break;
+    case 4: net_sort_padded<F, 4, K, V>(p, pv, n, flip); break;
+    case 5: net_sort_padded<F, 5, K, V>(p, pv, n, flip); break;
+    case 6: net_sort_padded<F, 6, K, V>(p, pv, n, flip); break;
+    case 7: net_sort_padded<F, 7, K, V>(p, pv, n, flip); break;
+    case 8: net_sort_padded<F, 8, K, V>(p, pv, n, flip); break;
+    case 9: net_sort_padded<F, 9, K, V>(p, pv, n, flip); break;
+    case 10: net_sort_padded<F, 10, K, V>(p, pv, n, flip); break;
+    case 11: net_sort_padded<F, 11, K, V>(p, pv, n, flip); break;
+    case 12: net_sort_padded<F, 12, K, V>(p, pv, n, flip); break;
+    case 13: net_sort_padded<F, 13, K, V>(p, pv, n, flip); break;
+    case 14: net_sort_padded<F, 14, K, V>(p, pv, n, flip); break;
+    case 15: net_sort_padded<F, 15, K, V>(p, pv, n, flip); break;
+    default: net_sort_padded<F, 16, K, V>(p, pv, n, flip); break;
   }
 }
 
@@ -242,15 +312,21 @@ struct SortArgs {
   int waves;      // resident waves of a per-class launch (plain baseline)
   int k0[3];
   int interleave;  // alternate RSS and network tiles in the persistent kernel
+  int net_mix;     // class 0 holds every network size, in batch order
 };
 
 // Kind sets of the persistent kernels: every class (one kernel holding every
-// handler), the network classes, or one RSS class (17..64, 65..128, 129..256).
-constexpr int kKindAll = 0, kKindNet = 1, kKindRss16 = 2, kKindRss32 = 3, kKindRss64 = 4, kKinds = 5;
+// handler), the network classes (per size, or mixed sizes in batch order), or
+// one RSS class (17..64, 65..128, 129..256).
+constexpr int kKindAll = 0, kKindNet = 1, kKindRss16 = 2, kKindRss32 = 3, kKindRss64 = 4, kKindNetMix = 5,
+              kKinds = 6;
+static_assert(kCtrlTile + kKinds * kTileParts * 32 <= kCtrlWords, "claim counters must fit ctrl");
+
+__host__ __device__ constexpr bool is_net_kind(int ks) { return ks == kKindNet || ks == kKindNetMix; }
 
 __host__ __device__ __forceinline__ bool in_kind(int c, int ks) {
   if (ks == kKindAll) return true;
-  if (ks == kKindNet) return c < kNetClasses;
+  if (is_net_kind(ks)) return c < kNetClasses;
   return c == kNetClasses + (ks - kKindRss16);
 }
 
@@ -261,9 +337,12 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint3
                                          K flip, int c, int tile_in_class, int count, int list, int waves) {
   const int rounds = class_rounds(c, count, a.rounds, waves, kPersistTpw);
   const int first = tile_in_class * class_tile(c, rounds);
-  if constexpr (KS == kKindAll || KS == kKindNet) {
+  if constexpr (KS == kKindAll || is_net_kind(KS)) {
     if (c < kNetClasses) {
-      net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
+      if (KS == kKindNetMix || (KS == kKindAll && a.net_mix))
+        net_tile_mixed<F, K, V>(keys, vals, a.offsets, a.ids, list, count, first, flip);
+      else
+        net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
       return;
     }
   }
@@ -339,14 +418,14 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
 template <class K, bool V, int KS> struct PersistWaves {
   static constexpr int kType = (sizeof(K) == 8 ? 2 : 0) + (V ? 1 : 0);  // u32, u32+v, u64, u64+v
   static constexpr int value = KS == kKindAll   ? (kType == 0 ? 5 : (kType == 3 ? 3 : 4))
-                               : KS == kKindNet ? 1
+                               : is_net_kind(KS) ? 1
                                : kType == 0     ? 6
                                : (kType == 1 && KS == kKindRss16) ? 5
                                                                   : 4;
 };
 
 template <class K, bool V, int KS> struct PersistLds {
-  static constexpr size_t kBytes = KS == kKindNet     ? 16
+  static constexpr size_t kBytes = is_net_kind(KS)   ? 16
                                    : KS == kKindRss16 ? 4 * sizeof(GroupLds<K, V, 16>)
                                    : KS == kKindRss32 ? 2 * sizeof(GroupLds<K, V, 32>)
                                    : KS == kKindRss64 ? sizeof(GroupLds<K, V, 64>)
@@ -369,7 +448,7 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
   const int wi = ((int)blockIdx.x / kTileParts) * kSortWaves + wave;  // wave index within the partition
   uint32_t* counter = &ctrl[kCtrlTile + (KS * kTileParts + part) * 32];
 
-  constexpr bool kSingle = KS >= kKindRss16;
+  constexpr bool kSingle = KS >= kKindRss16 && KS <= kKindRss64;
   if constexpr (kSingle) {
     // One RSS class, in units of one round (one array per lane group).
     // Partition p owns a contiguous range of units; its waves take chunks of
@@ -413,9 +492,9 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
     else
       t_net += n;
   }
-  // the network-only kernel keeps its class prefix in registers
+  // the network-only kernels keep their class prefix in registers
   int net_first[kNetClasses + 1];
-  if constexpr (KS == kKindNet) {
+  if constexpr (is_net_kind(KS)) {
     int acc = 0;
 #pragma unroll
     for (int o = 0; o < kNetClasses; ++o) {
@@ -431,7 +510,7 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
   // tile from one device-wide counter costs more: atomics on one line from all
   // XCDs serialise.)
   auto process = [&](int t) {
-    if constexpr (KS == kKindNet) {
+    if constexpr (is_net_kind(KS)) {
       int c = 0, idx = 0;
 #pragma unroll
       for (int o = 0; o < kNetClasses; ++o) {
@@ -547,6 +626,7 @@ inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
   a.k0[1] = tuning().rss_k[1];
   a.k0[2] = tuning().rss_k[2];
   a.interleave = tuning().interleave;
+  a.net_mix = tuning().net_mix;
   return a;
 }
 
@@ -569,9 +649,10 @@ struct SegLaunch {
   uint32_t* vals;
   SortArgs args;
   K flip;
-  void* p_count[4];
+  int mix;  // binning mixes the network sizes (persistent forms only)
+  void* p_count[5];
   void* p_scan[3];
-  void* p_scatter[5];
+  void* p_scatter[6];
   void* p_sort[5];
   bool split;
   int persist_blocks[kKinds];  // grid of the persistent kernel per kind set
@@ -581,7 +662,7 @@ struct SegLaunch {
   int node_kind(int i) const {
     if (!split) return kKindAll;
     static constexpr int order[4] = {kKindNet, kKindRss64, kKindRss32, kKindRss16};
-    return order[i - 3];
+    return (i == 3 && mix) ? kKindNetMix : order[i - 3];
   }
 
   void fill(DeviceCtx* c, SegmentedCache* s, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
@@ -598,16 +679,18 @@ struct SegLaunch {
     vals = v;
     args = make_args(off, s);
     flip = fl;
-    p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status;
+    mix = args.net_mix;
+    p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status; p_count[4] = &mix;
     p_scan[0] = &blockhist; p_scan[1] = &nblocks; p_scan[2] = &ctrl;
     p_scatter[0] = &offsets; p_scatter[1] = &nseg; p_scatter[2] = &blockbase; p_scatter[3] = &ctrl_c;
-    p_scatter[4] = &ids;
+    p_scatter[4] = &ids; p_scatter[5] = &mix;
     p_sort[0] = &keys; p_sort[1] = &vals; p_sort[2] = &args; p_sort[3] = &ctrl; p_sort[4] = &flip;
   }
 
   static void* kernel_of(int ks) {
     switch (ks) {
       case kKindNet: return (void*)seg_persistent_kernel<F, K, V, kKindNet>;
+      case kKindNetMix: return (void*)seg_persistent_kernel<F, K, V, kKindNetMix>;
       case kKindRss16: return (void*)seg_persistent_kernel<F, K, V, kKindRss16>;
       case kKindRss32: return (void*)seg_persistent_kernel<F, K, V, kKindRss32>;
       case kKindRss64: return (void*)seg_persistent_kernel<F, K, V, kKindRss64>;
@@ -652,10 +735,10 @@ struct SegLaunch {
 
   hipError_t launch_binning(hipStream_t s) {
     hipLaunchKernelGGL(seg_count_kernel, dim3(kBinBlocks), dim3(kBinThreads), 0, s, offsets, nseg, blockhist,
-                       status);
+                       status, mix);
     hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, blockhist, nblocks, ctrl);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(kBinBlocks), dim3(kBinThreads), 0, s, offsets, nseg, blockbase,
-                       ctrl_c, ids);
+                       ctrl_c, ids, mix);
     return hipGetLastError();
   }
   hipError_t launch_direct(hipStream_t s) {
@@ -679,6 +762,8 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
       nb <= 0)
     nb = 2;
   L.args.waves = nb * c->num_cus * kSortWaves;
+  L.args.net_mix = 0;  // the baseline launches one kernel per network size
+  L.mix = 0;
   hipError_t e = L.launch_binning(s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, (kCtrlStart + kClasses) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -710,7 +795,7 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
 
 template <int F, class K, bool V>
 static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
-  const int key = ((int)sizeof(K) * 4 + (V ? 2 : 0) + F) * 2 + (L.split ? 1 : 0);
+  const int key = (((int)sizeof(K) * 4 + (V ? 2 : 0) + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0);
   GraphEntry* g = nullptr;
   for (GraphEntry& ge : sc->graphs)
     if (ge.key == key && std::equal(ge.persist_blocks, ge.persist_blocks + kKinds, L.persist_blocks)) g = &ge;
@@ -750,6 +835,7 @@ static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* v
   for (int& b : L.persist_blocks) b = 0;
   if (L.split) {
     L.persist_blocks[kKindNet] = persistent_blocks<F, K, V, kKindNet>(c);
+    L.persist_blocks[kKindNetMix] = persistent_blocks<F, K, V, kKindNetMix>(c);
     L.persist_blocks[kKindRss16] = persistent_blocks<F, K, V, kKindRss16>(c);
     L.persist_blocks[kKindRss32] = persistent_blocks<F, K, V, kKindRss32>(c);
     L.persist_blocks[kKindRss64] = persistent_blocks<F, K, V, kKindRss64>(c);

@@ -216,3 +216,40 @@ def test_first_level_bucket_counts_with_payload(k, mode):
     finally:
         for n, v in zip(names, old):
             ss.set_tuning(n, v)
+
+
+@pytest.mark.parametrize("mode", [ss.MODE_AUTO, ss.MODE_PERSISTENT], ids=["graph", "persistent"])
+@pytest.mark.parametrize("dtype", TYPES, ids=lambda d: np.dtype(d).name)
+def test_mixed_size_network_tiles(dtype, mode):
+    """net_mix = 1: segments of 2..16 keys sorted in batch order with the
+    network of each wave's largest segment (max padding), with and without
+    payload, next to RSS segments and empty/size-1 segments."""
+    old = ss.get_tuning("net_mix")
+    ss.set_tuning("net_mix", 1)
+    try:
+        rng = np.random.default_rng(11)
+        sizes = np.concatenate([rng.integers(0, 17, size=5000), rng.integers(17, 257, size=300),
+                                np.arange(0, 17)])
+        rng.shuffle(sizes)
+        off = inputs.offsets_from_sizes(sizes)
+        total = int(off[-1])
+        # keys only, duplicate-heavy and extreme values included
+        keys = inputs.random_keys(dtype, total, seed=12)
+        info = np.iinfo(dtype)
+        keys[rng.random(total) < 0.2] = info.max
+        keys[rng.random(total) < 0.1] = info.min
+        got, _ = run_seg(keys, off, mode=mode)
+        want, _ = oracle.sort_segments(keys, off)
+        assert (got == want).all(), first_mismatch(got, want)
+        # payload with distinct keys: exact
+        dk = inputs.distinct_u64(total, seed=13)
+        dk = dk.view(dtype) if np.dtype(dtype).itemsize == 8 else \
+            (np.random.default_rng(13).permutation(total).astype(np.int64) * 7 + 3).astype(dtype)
+        vals = inputs.segment_index_payload(off)
+        gk, gv = run_seg(dk, off, vals, mode=mode)
+        wk, wv = oracle.sort_segments(dk, off, vals)
+        assert (gk == wk).all(), first_mismatch(gk, wk)
+        assert (gv == wv).all(), first_mismatch(gv, wv)
+        assert ss.device_status() == 0
+    finally:
+        ss.set_tuning("net_mix", old)
