@@ -36,6 +36,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+MALL_BYTES = 256 << 20  # Infinity Cache of one MI355X
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
@@ -45,7 +46,7 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="all",
-                   choices=["all", "fixed16_u32", "config1", "config2", "rss", "ragged", "serve"])
+                   choices=["all", "fixed16_u32", "config1", "config2", "rss", "rss_classes", "ragged", "serve"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extras", action="store_true", help="headline workload only")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -190,7 +191,21 @@ def cpu_baseline_fixed(seconds, n=16):
             break
     return {"value": done * n / el, "unit": "keys/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} arrays of {n} uint32 keys (uniform; one set of {count} arrays sorted "
-                      f"from a fresh copy per pass), {threads} host threads, {el:.1f} s"}
+                      f"from a fresh copy per pass), {threads} host threads, {el:.1f} s",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host that ran the oracle."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def bench_config1(args):
@@ -246,13 +261,24 @@ def bench_config2(args):
             row = {}
             for dist in ("uniform", "few", "sorted", "reverse"):
                 a = device_fixed_keys(torch, dtype, n, count, dist, gen).reshape(-1)
-                ms = time_inplace(lambda: ss.sort_small(a, n), 5, 2)
-                row[dist] = {"ms": ms, "keys_per_s": count * n / (ms * 1e-3), **rate(2 * count * n * kb, ms)}
-                del a
+                # footprints that fit the 256 MB MALL rotate over 4 buffers (1 GiB), so
+                # every call streams from HBM
+                bufs = [a] if count * n * kb > MALL_BYTES else [a] + [a.clone() for _ in range(3)]
+                calls = [0]
+
+                def step():
+                    ss.sort_small(bufs[calls[0] % len(bufs)], n)
+                    calls[0] += 1
+
+                ms = time_inplace(step, 8, 4)
+                row[dist] = {"ms": ms, "keys_per_s": count * n / (ms * 1e-3), **rate(2 * count * n * kb, ms),
+                             "buffers": len(bufs)}
+                del a, bufs
             out[f"{dtype}_n{n}"] = row
     torch.cuda.empty_cache()
     return {"workload": "2^24 arrays per n, stride n; time per call (the networks are data-oblivious, "
-                        "so repeated in-place calls do identical work)", "results": out}
+                        "so repeated in-place calls do identical work); inputs of at most 256 MB rotate "
+                        "over 4 buffers", "results": out}
 
 
 def seg_bytes(total, nseg, key_bytes, has_vals):
@@ -277,6 +303,30 @@ def bench_rss(args, dist="uniform", nseg=1 << 20, steps=10, warmup=2):
     torch.cuda.empty_cache()
     return {"workload": f"RSS, {nseg} CSR arrays, n uniform in [17,256], int32 {dist}", "keys": total,
             "nseg": nseg, **res}
+
+
+def bench_rss_classes(args, nseg=1 << 20, steps=5, warmup=2):
+    """2^20 CSR arrays per size class (17..32, 33..64, 65..128, 129..256), int32 uniform."""
+    import torch
+    import paper_2002_05599_amd as ss
+    from paper_2002_05599_amd import inputs
+    out = {}
+    for lo, hi in ((17, 32), (33, 64), (65, 128), (129, 256)):
+        off = inputs.offsets_from_sizes(inputs.csr_sizes(nseg, lo, hi, seed=hi))
+        total = int(off[-1])
+        tk = torch.from_numpy(inputs.random_keys(np.int32, total, seed=lo)).cuda()
+        to = torch.from_numpy(off).cuda()
+        bufs = StepBuffers((tk,), steps)
+        row = {}
+        for name, mode in (("graph", ss.MODE_AUTO), ("plain", ss.MODE_PLAIN)):
+            ms, _ = time_steps(lambda b: ss.segmented_sort(b[0], to, mode=mode), bufs, steps, warmup)
+            row[name] = {"ms": ms, "keys_per_s": total / (ms * 1e-3), **rate(seg_bytes(total, nseg, 4, False), ms)}
+        out[f"{lo}..{hi}"] = {"keys": total, **row}
+        del bufs, tk, to
+        torch.cuda.empty_cache()
+    assert ss.device_status() == 0
+    return {"workload": f"RSS per size class, {nseg} CSR arrays each, n uniform in the class, int32 uniform",
+            "classes": out}
 
 
 def bench_ragged(args, nseg=10_000_000, steps=10, warmup=2):
@@ -369,6 +419,7 @@ def main():
             ex["config2"] = bench_config2(args)
             ex["config3_uniform"] = bench_rss(args, "uniform")
             ex["config3_zipf"] = bench_rss(args, "zipf")
+            ex["config3_per_class"] = bench_rss_classes(args)
             ex["config4"] = bench_ragged(args)
             ex["config5"] = bench_serve(args)
             out["extras"] = ex
@@ -379,6 +430,8 @@ def main():
     elif w == "rss":
         out = {"rss_uniform": bench_rss(args, "uniform", steps=args.steps, warmup=args.warmup),
                "rss_zipf": bench_rss(args, "zipf", steps=args.steps, warmup=args.warmup)}
+    elif w == "rss_classes":
+        out = bench_rss_classes(args)
     elif w == "ragged":
         out = bench_ragged(args, steps=args.steps, warmup=args.warmup)
     else:
