@@ -30,7 +30,9 @@
  *   - Working memory of the segmented path (counters, size-class lists,
  *     cached graph) is allocated per (device, stream) on first use and grown
  *     (after a device synchronisation) when a larger batch arrives; calls of
- *     the same or smaller shape allocate nothing.
+ *     the same or smaller shape allocate nothing.  It is kept until the
+ *     process ends (about 4 bytes per segment of the largest batch plus 80 KB
+ *     per stream), so a caller should not churn through short-lived streams.
  *   - Calls are thread-safe.  Segmented sorts on different streams use
  *     separate working memory and may overlap on the device; calls on one
  *     stream are ordered by that stream.

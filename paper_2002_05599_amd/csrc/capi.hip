@@ -15,9 +15,13 @@
 
 namespace ss {
 
-Tuning& tuning() {
-  static Tuning t;
-  return t;
+// The process-wide tuning values; read and written only under g_tune_mu.
+static std::mutex g_tune_mu;
+static Tuning g_tuning;
+
+Tuning tuning() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return g_tuning;
 }
 
 static std::mutex g_ctx_mu;
@@ -127,8 +131,9 @@ struct TuneEntry {
   bool pow2_k;  // a bucket count: a power of two in [lo, hi]
 };
 
+// Entries point into g_tuning: use under g_tune_mu.
 static std::vector<TuneEntry> tune_table() {
-  Tuning& t = tuning();
+  Tuning& t = g_tuning;
   return {
       {"family", &t.family, 0, 1, false},
       {"rss_k_small", &t.rss_k[0], 4, 16, true},
@@ -141,8 +146,6 @@ static std::vector<TuneEntry> tune_table() {
       {"net_mix", &t.net_mix, 0, 1, false},
   };
 }
-
-static std::mutex g_tune_mu;
 
 static ss_status set_tuning(const char* name, int64_t value) {
   if (!name) return SS_ENOTUNE;

@@ -16,7 +16,7 @@ struct Tuning {
   int persist_split = 1;  // 1: one persistent kernel per kind (networks, each RSS class); 0: one for all
   int net_mix = 0;        // 1: persistent forms sort 2..16-key segments in batch order, mixed sizes
 };
-Tuning& tuning();
+Tuning tuning();  // a consistent copy of the current settings
 
 // Fixed layout, n = 2..16 (networks).  flip = sign-bit mask (0 for unsigned).
 hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,

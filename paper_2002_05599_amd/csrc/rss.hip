@@ -36,7 +36,7 @@ static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, K 
 
 template <int F, class K>
 static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
-  const Tuning& t = tuning();
+  const Tuning t = tuning();
   if (n <= 64) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], s);
   if (n <= 128) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], s);
   return launch_rss_g<F, K, 64>(keys, n, count, stride, flip, t.rss_k[2], s);

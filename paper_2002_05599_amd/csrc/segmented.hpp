@@ -616,17 +616,18 @@ static int persistent_blocks(DeviceCtx* c) {
 }
 
 inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
+  const Tuning t = tuning();
   SortArgs a;
   a.offsets = offsets;
   a.ids = s->ids;
   a.ctrl = s->ctrl;
-  a.rounds = tuning().rss_rounds;
+  a.rounds = t.rss_rounds;
   a.waves = 1;
-  a.k0[0] = tuning().rss_k[0];
-  a.k0[1] = tuning().rss_k[1];
-  a.k0[2] = tuning().rss_k[2];
-  a.interleave = tuning().interleave;
-  a.net_mix = tuning().net_mix;
+  a.k0[0] = t.rss_k[0];
+  a.k0[1] = t.rss_k[1];
+  a.k0[2] = t.rss_k[2];
+  a.interleave = t.interleave;
+  a.net_mix = t.net_mix;
   return a;
 }
 
