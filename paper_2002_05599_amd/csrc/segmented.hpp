@@ -419,7 +419,7 @@ template <class K, bool V, int KS> struct PersistWaves {
   static constexpr int kType = (sizeof(K) == 8 ? 2 : 0) + (V ? 1 : 0);  // u32, u32+v, u64, u64+v
   static constexpr int value = KS == kKindAll   ? (kType == 0 ? 5 : (kType == 3 ? 3 : 4))
                                : is_net_kind(KS) ? 1
-                               : kType == 0     ? 6
+                               : kType == 0     ? (KS == kKindRss16 ? 7 : 6)
                                : (kType == 1 && KS == kKindRss16) ? 5
                                                                   : 4;
 };
