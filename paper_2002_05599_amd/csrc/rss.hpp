@@ -205,11 +205,13 @@ __device__ __forceinline__ K lane_xor_key(K x) {
 
 // Compare-exchange with the lane J apart: the lane whose bit B is clear keeps
 // the minimum, the other the maximum.
+// (The lower lane takes y if y < x, the upper one if not: with equal keys
+// either choice gives the same value, so one compare and one select suffice.)
 template <int J, int B, class K>
 __device__ __forceinline__ K team_exchange(K x, int t) {
   const K y = lane_xor_key<J>(x);
-  const bool lower = (t & B) == 0;
-  return lower ? (y < x ? y : x) : (y < x ? x : y);
+  const bool upper = (t & B) != 0;
+  return ((y < x) != upper) ? y : x;
 }
 
 template <int KBLK, int J, class K>
