@@ -6,13 +6,16 @@ one comparator network per array.  A step is one sort call over the whole
 batch (one kernel launch) on its own fresh, unsorted copy of the input, which
 is resident in HBM before the timed region starts.
 
-Printed as one JSON line: keys/s, the roofline of the dominant kernel
-(algorithmic HBM bytes per launch / its event-timed duration, against 8 TB/s),
-HBM traffic per launch from the committed counter summary (only while the
+The LAST line on stdout is the compact headline JSON: keys/s, the roofline
+of the dominant kernel (algorithmic HBM bytes per launch / its event-timed
+duration, against 8 TB/s, beside the measured device-copy ceiling), HBM
+traffic per launch from the committed counter summary (only while the
 kernel source is unchanged), and the CPU oracle timed on a bounded sample on
-the host cores.  Unless --no-extras, the line also carries ``extras``: every
-other workload --
+the host cores.  Unless --no-extras, every other workload runs first and
+prints one JSON line of its own (``{"extra": name, ...}``), and all of them
+are also written to --extras-out:
 
+  copy_ceiling  device-to-device copy of 1 GiB: runtime copy, streaming probe
   config1  100,000 arrays of 8 uint32 keys (launch-to-completion latency)
   config2  n = 2..16, 2^24 arrays, uint32 and int64, four distributions
   config3  Register Sample Sort, 2^20 CSR arrays of 17..256 int32 keys,
@@ -46,10 +49,13 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="all",
-                   choices=["all", "fixed16_u32", "config1", "config2", "rss", "rss_classes", "ragged", "serve"])
+                   choices=["all", "fixed16_u32", "copy", "config1", "config2", "rss", "rss_classes", "ragged",
+                            "serve"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extras", action="store_true", help="headline workload only")
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--extras-out", default=os.path.join(ROOT, "gpurun_out", "bench_extras.json"),
+                   help="file for the extra workloads' results (also printed one per line)")
     return p.parse_args()
 
 
@@ -174,25 +180,63 @@ def bench_fixed16(args):
     }
 
 
+def cpu_share():
+    """Host threads this process may use: its CPU affinity, capped at the CPU
+    share a one-GPU machine gives a job (16 threads)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(avail, 16))
+
+
 def cpu_baseline_fixed(seconds, n=16):
-    """The oracle (insertion sort at n <= 16) on a bounded sample, all host threads."""
+    """The oracle (insertion sort at n <= 16) timed on a bounded sample of the
+    headline workload: built with gcc -O3 -march=native on this host (the
+    paper's compiler settings, Section 4.1), run (a) on one thread pinned to
+    one core, like the paper's taskset runs, and (b) on every thread of this
+    process's CPU share.  Each pass sorts a fresh copy of the sample in place;
+    the copy is restored outside the timed region.  Median of the passes."""
+    import tempfile
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
-    count = 1 << 18
+    from oracle import build as oracle_build
+    tmp = tempfile.mkdtemp(prefix="oracle_native_")
+    lib = oracle.load(oracle_build.build_native(os.path.join(tmp, "liboracle_native.so")))
+    count = 1 << 18  # 4 M keys, 16 MiB: far above the host's last-level cache per core
     src = np.random.default_rng(9).integers(0, 2**32, size=count * n, dtype=np.uint64).astype(np.uint32)
-    oracle.sort_fixed(src[: n * 1024], n, 1024, n)
-    done = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.sort_fixed(src, n, count, n, threads=threads)  # sorts a fresh copy each pass
-        done += count
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": done * n / el, "unit": "keys/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} arrays of {n} uint32 keys (uniform; one set of {count} arrays sorted "
-                      f"from a fresh copy per pass), {threads} host threads, {el:.1f} s",
-            "host": host_cpu()}
+    work = src.copy()
+
+    def run(threads, budget):
+        oracle.sort_fixed_inplace(work, n, count, n, lib=lib, threads=threads)  # warm-up
+        times = []
+        t_end = time.perf_counter() + budget
+        while len(times) < 3 or (time.perf_counter() < t_end and len(times) < 200):
+            np.copyto(work, src)
+            t0 = time.perf_counter()
+            oracle.sort_fixed_inplace(work, n, count, n, lib=lib, threads=threads)
+            times.append(time.perf_counter() - t0)
+        return count * n / float(np.median(times)), len(times)
+
+    cores = cpu_share()
+    single_core = None
+    old_aff = None
+    try:
+        old_aff = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old_aff)})
+        single_core = min(old_aff)
+    except (AttributeError, OSError):
+        pass
+    try:
+        one, n_one = run(1, seconds * 0.6)
+    finally:
+        if old_aff is not None:
+            os.sched_setaffinity(0, old_aff)
+    many, n_many = run(cores, seconds * 0.4)
+    return {"value": many, "unit": "keys/s", "cores": cores, "kind": "oracle",
+            "sample": f"{count} arrays x {n} uint32 keys (16 MiB, uniform), in place, median of {n_many} "
+                      f"passes on {cores} threads; single thread pinned to core {single_core}: "
+                      f"{one:.4g} keys/s ({n_one} passes); gcc -O3 -march=native",
+            "single_thread_value": one, "host": host_cpu()}
 
 
 def host_cpu():
@@ -206,6 +250,24 @@ def host_cpu():
     except OSError:
         pass
     return {"model": model, "logical_cpus": os.cpu_count()}
+
+
+def bench_copy_ceiling(args, nbytes=1 << 30, steps=20, warmup=3):
+    """Device-to-device copy of 1 GiB (2 GiB moved): the runtime's copy and the
+    library's streaming copy probe -- the practical ceiling of a kernel that
+    reads and writes every byte once."""
+    import torch
+    import paper_2002_05599_amd as ss
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").random_()
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn in (("runtime_copy", lambda: dst.copy_(src)), ("stream_copy", lambda: ss.stream_copy(dst, src))):
+        ms = time_inplace(fn, steps, warmup)
+        out[name] = {"ms": ms, **rate(2 * nbytes, ms)}
+    assert torch.equal(dst, src)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"workload": "device-to-device copy of 1 GiB (2 GiB moved)", **out}
 
 
 def bench_config1(args):
@@ -401,6 +463,28 @@ def bench_serve(args, pool=16, rhos=(0.5, 0.8), n_open=300):
     return out
 
 
+def compact(x, digits=4):
+    """Round floats so the extras lines stay short."""
+    if isinstance(x, float):
+        return float(f"{x:.{digits}g}")
+    if isinstance(x, dict):
+        return {k: compact(v, digits) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [compact(v, digits) for v in x]
+    return x
+
+
+EXTRAS = [
+    ("config1", bench_config1),
+    ("config2", bench_config2),
+    ("config3_uniform", lambda a: bench_rss(a, "uniform")),
+    ("config3_zipf", lambda a: bench_rss(a, "zipf")),
+    ("config3_per_class", bench_rss_classes),
+    ("config4", bench_ragged),
+    ("config5", bench_serve),
+]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -412,19 +496,26 @@ def main():
     torch.cuda.set_device(0)
     w = args.workload
     if w in ("all", "fixed16_u32"):
+        ceiling = bench_copy_ceiling(args)
         out = bench_fixed16(args)
+        out["roofline"]["copy_ceiling_GBps"] = {k: round(ceiling[k]["GBps"], 1)
+                                                for k in ("runtime_copy", "stream_copy")}
         if not args.no_cpu:
             out["cpu_baseline"] = cpu_baseline_fixed(args.cpu_seconds)
         if w == "all" and not args.no_extras:
-            ex = {}
-            ex["config1"] = bench_config1(args)
-            ex["config2"] = bench_config2(args)
-            ex["config3_uniform"] = bench_rss(args, "uniform")
-            ex["config3_zipf"] = bench_rss(args, "zipf")
-            ex["config3_per_class"] = bench_rss_classes(args)
-            ex["config4"] = bench_ragged(args)
-            ex["config5"] = bench_serve(args)
-            out["extras"] = ex
+            extras = {"copy_ceiling": ceiling}
+            print(json.dumps({"extra": "copy_ceiling", **compact(ceiling)}), flush=True)
+            for name, fn in EXTRAS:
+                res = compact(fn(args))
+                extras[name] = res
+                print(json.dumps({"extra": name, **res}), flush=True)
+            if args.extras_out:
+                os.makedirs(os.path.dirname(os.path.abspath(args.extras_out)), exist_ok=True)
+                with open(args.extras_out, "w") as f:
+                    json.dump(extras, f, indent=1)
+                out["extras_file"] = args.extras_out
+    elif w == "copy":
+        out = bench_copy_ceiling(args)
     elif w == "config1":
         out = bench_config1(args)
     elif w == "config2":
@@ -438,7 +529,8 @@ def main():
         out = bench_ragged(args, steps=args.steps, warmup=args.warmup)
     else:
         out = bench_serve(args)
-    print(json.dumps(out), flush=True)
+    # the headline is the last line on stdout, compact
+    print(json.dumps(compact(out, 6), separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

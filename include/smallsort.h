@@ -14,7 +14,8 @@
  *     caller owns every buffer; the library never frees or retains them.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *     work is enqueued asynchronously on it; no call synchronises the host,
- *     except ss_device_status, which says so.
+ *     except ss_device_status and the SS_MODE_PLAIN baseline of
+ *     ss_segmented_sort, which say so.
  *   - Sorting is in place and ascending (non-decreasing): the lower channel of
  *     every comparator receives the smaller key (Section 2.1).
  *   - Signed keys are ordered as two's-complement integers.
@@ -28,10 +29,12 @@
  *     decreasing offset) are recorded in a per-device status word, read with
  *     ss_device_status; the affected segment is left unsorted.
  *   - Working memory of the segmented path (counters, size-class lists,
- *     cached graph) is allocated per (device, stream) on first use and grown
- *     (after a device synchronisation) when a larger batch arrives; calls of
+ *     cached graph) is allocated per (device, stream) on first use.  When a
+ *     larger batch arrives its segment list is grown in stream order
+ *     (hipFreeAsync / hipMallocAsync on the call's stream, which is the only
+ *     stream that uses it), with no host or device synchronisation; calls of
  *     the same or smaller shape allocate nothing.  It is kept until the
- *     process ends (about 4 bytes per segment of the largest batch plus 80 KB
+ *     process ends (about 5 bytes per segment of the largest batch plus 80 KB
  *     per stream), so a caller should not churn through short-lived streams.
  *   - Calls are thread-safe.  Segmented sorts on different streams use
  *     separate working memory and may overlap on the device; calls on one
@@ -109,7 +112,9 @@ ss_status segmented_sort_i64(int64_t *keys, uint32_t *vals, const int32_t *offse
  * Generic segmented entry point: key_type is an SS_KEY_* code, mode an
  * SS_MODE_* code.  Same layout, ownership and errors as segmented_sort_*;
  * SS_EINVAL for an unknown key_type or mode.  SS_MODE_PLAIN is the
- * per-size-class baseline the persistent form is measured against.
+ * per-size-class baseline the persistent form is measured against: it reads
+ * the class counts back to the host to size one launch per class, so it
+ * synchronises `stream` in the middle of the call (the other modes do not).
  */
 ss_status ss_segmented_sort(int32_t key_type, void *keys, uint32_t *vals, const int32_t *offsets,
                             int32_t nseg, int32_t mode, void *stream);
@@ -145,6 +150,11 @@ const char *ss_strerror(ss_status status);
  *                  (neighbouring segments share cache lines); 0: one class
  *                  per size, each with its exact network.  The plain form
  *                  always uses one class per size.
+ *   "rss_level_cap" levels of Register Sample Sort (1..8, default 8) after
+ *                  which a bucket still above 16 keys is finished by a
+ *                  rank-counting sort (each key placed at the number of keys
+ *                  that precede it); lower values exist to test and measure
+ *                  that fallback.
  * ss_set_tuning_value returns SS_ENOTUNE for an unknown name, SS_EINVAL for a
  * value out of range.  ss_get_tuning_value returns -1 for an unknown name.
  * ss_load_tuning reads a flat JSON object {"name": integer, ...} with these
@@ -154,6 +164,17 @@ const char *ss_strerror(ss_status status);
 ss_status ss_set_tuning_value(const char *name, int64_t value);
 int64_t ss_get_tuning_value(const char *name);
 ss_status ss_load_tuning(const char *json_path);
+
+/*
+ * Streaming device-to-device copy of `bytes` bytes from src to dst, with the
+ * access pattern of the fixed-layout sorting kernels (16-byte nontemporal
+ * loads and stores, consecutive lanes on consecutive chunks).  It is the
+ * practical ceiling a read-once / write-once kernel reaches on this device,
+ * against which the sorts are measured.  dst and src are device pointers of
+ * non-overlapping buffers.  Errors: SS_EINVAL for bytes < 0 or a NULL pointer
+ * with bytes > 0; SS_EALIGN unless both pointers and bytes are multiples of 16.
+ */
+ss_status ss_stream_copy(void *dst, const void *src, int64_t bytes, void *stream);
 
 /* Library version string, e.g. "smallsort 0.1 gfx950". */
 const char *ss_version(void);

@@ -128,6 +128,28 @@ def sort_fixed(keys, n, count, stride, lib=None, threads=1):
     return k
 
 
+def sort_fixed_inplace(k, n, count, stride, lib=None, threads=1):
+    """Like sort_fixed, but sorts the numpy array ``k`` in place (no copy), so a
+    timing loop can restore its input outside the timed region."""
+    if count * stride > k.size and count > 0:
+        raise ValueError("keys too short for count*stride")
+    f = getattr(_get(lib), f"oracle_sort_fixed_{_suffix(k)}")
+    item = k.itemsize
+    if threads <= 1 or count < 2 * threads:
+        _check(f(_ptr(k), n, count, stride))
+        return k
+    bounds = np.linspace(0, count, threads + 1).astype(np.int64)
+
+    def work(t):
+        lo, hi = int(bounds[t]), int(bounds[t + 1])
+        return f(k.ctypes.data + lo * stride * item, n, hi - lo, stride)
+
+    with ThreadPoolExecutor(threads) as ex:
+        for rc in ex.map(work, range(threads)):
+            _check(rc)
+    return k
+
+
 def sort_segments(keys, offsets, vals=None, lib=None, threads=1):
     """Sort CSR segments [offsets[i], offsets[i+1]); returns (keys, vals) copies."""
     k = np.array(keys, copy=True)

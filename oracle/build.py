@@ -19,5 +19,14 @@ def build(src: str = SRC, out: str = LIB, extra_flags=()) -> str:
     return out
 
 
+def build_native(out: str, src: str = SRC) -> str:
+    """The same source compiled as the paper compiled its sorters for timing
+    (gcc -O3 -march=native, Section 4.1), for the host that runs it.  Used
+    only to time the oracle as a CPU baseline; correctness tests load LIB."""
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-shared", "-fPIC", "-o", out, src]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(), file=sys.stderr)

@@ -17,7 +17,7 @@ import threading
 __all__ = [
     "SmallSortError", "lib", "lib_path", "sort_small", "segmented_sort", "device_status",
     "set_tuning", "get_tuning", "load_tuning", "tuning_path", "version", "KEY_CODES",
-    "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN",
+    "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN", "stream_copy",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,6 +41,7 @@ _SIGS = {
     "ss_get_tuning_value": (ctypes.c_int64, [ctypes.c_char_p]),
     "ss_load_tuning": (ctypes.c_int32, [ctypes.c_char_p]),
     "ss_version": (ctypes.c_char_p, []),
+    "ss_stream_copy": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P]),
 }
 
 _lock = threading.Lock()
@@ -194,6 +195,18 @@ def get_tuning(name: str) -> int:
 
 def load_tuning(path: str):
     _check(lib().ss_load_tuning(os.fsencode(path)), f"ss_load_tuning({path})")
+
+
+def stream_copy(dst, src, stream=None):
+    """Streaming device copy of ``src`` into ``dst`` (same byte size, 16-byte aligned)."""
+    _require_cuda(dst, "dst")
+    _require_cuda(src, "src")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src must have the same byte size")
+    _check(lib().ss_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                int(nbytes), _stream_ptr(stream)), "ss_stream_copy")
+    return dst
 
 
 def version() -> str:

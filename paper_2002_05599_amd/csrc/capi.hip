@@ -144,6 +144,7 @@ static std::vector<TuneEntry> tune_table() {
       {"interleave", &t.interleave, 0, 1, false},
       {"persist_split", &t.persist_split, 0, 1, false},
       {"net_mix", &t.net_mix, 0, 1, false},
+      {"rss_level_cap", &t.rss_level_cap, 1, 8, false},
   };
 }
 
@@ -230,6 +231,15 @@ const char* ss_strerror(ss_status status) {
     case SS_ENOTUNE: return "unknown tuning parameter or unreadable tuning file";
     default: return "unknown status";
   }
+}
+
+ss_status ss_stream_copy(void* dst, const void* src, int64_t bytes, void* stream) {
+  if (bytes < 0) return SS_EINVAL;
+  if (bytes == 0) return SS_OK;
+  if (!dst || !src) return SS_EINVAL;
+  if (reinterpret_cast<uintptr_t>(dst) % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0 || bytes % 16 != 0)
+    return SS_EALIGN;
+  return from_hip(launch_stream_copy(dst, src, bytes, static_cast<hipStream_t>(stream)));
 }
 
 ss_status ss_set_tuning_value(const char* name, int64_t value) { return set_tuning(name, value); }

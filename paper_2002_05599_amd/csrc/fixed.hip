@@ -239,6 +239,36 @@ static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, 
   }
 }
 
+// Streaming copy with the tile kernels' access pattern: each thread moves
+// 16-byte chunks with nontemporal loads and stores, consecutive lanes on
+// consecutive chunks, kCopyIters chunks per thread in flight.
+constexpr int kCopyIters = 4;
+__global__ void __launch_bounds__(kTileThreads)
+stream_copy_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src, int64_t chunks) {
+  const int64_t base = (int64_t)blockIdx.x * (kTileThreads * kCopyIters) + threadIdx.x;
+  u32x4 buf[kCopyIters];
+#pragma unroll
+  for (int i = 0; i < kCopyIters; ++i) {
+    const int64_t c = base + (int64_t)i * kTileThreads;
+    if (c < chunks) buf[i] = __builtin_nontemporal_load(src + c);
+  }
+#pragma unroll
+  for (int i = 0; i < kCopyIters; ++i) {
+    const int64_t c = base + (int64_t)i * kTileThreads;
+    if (c < chunks) __builtin_nontemporal_store(buf[i], dst + c);
+  }
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t s) {
+  const int64_t chunks = bytes / 16;
+  const int64_t per_block = (int64_t)kTileThreads * kCopyIters;
+  const int64_t blocks = (chunks + per_block - 1) / per_block;
+  if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(kTileThreads), 0, s,
+                     static_cast<u32x4*>(dst), static_cast<const u32x4*>(src), chunks);
+  return hipGetLastError();
+}
+
 hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
                             hipStream_t s) {
   return tuning().family == 1 ? launch_fixed_f<1>(keys, n, count, stride, flip, s)

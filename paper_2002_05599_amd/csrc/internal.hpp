@@ -15,6 +15,7 @@ struct Tuning {
   int interleave = 1;    // persistent kernel alternates RSS and network tiles
   int persist_split = 1;  // 1: one persistent kernel per kind (networks, each RSS class); 0: one for all
   int net_mix = 0;        // 1: persistent forms sort 2..16-key segments in batch order, mixed sizes
+  int rss_level_cap = 8;  // RSS levels before the rank-counting fallback finishes a pending bucket
 };
 Tuning tuning();  // a consistent copy of the current settings
 
@@ -29,6 +30,10 @@ hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t st
                                 int* status, hipStream_t s);
 hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
                                 int* status, hipStream_t s);
+
+// Streaming device-to-device copy of `bytes` (the read-once / write-once
+// ceiling the sorting kernels are measured against).
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
 
 // Per-device context: status word, device properties and working memory
 // for the segmented path (grown on demand, freed at process exit).

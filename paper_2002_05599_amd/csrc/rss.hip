@@ -12,7 +12,7 @@ constexpr int kRssWaves = kRssThreads / kWave;
 
 template <int F, class K, int G>
 __global__ void __launch_bounds__(kRssThreads)
-rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip, int k0) {
+rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip, int k0, int level_cap) {
   constexpr int kGroups = kWave / G;
   __shared__ GroupLds<K, false, G> lds[kRssWaves * kGroups];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
@@ -20,26 +20,26 @@ rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K f
   const int64_t arr = ((int64_t)blockIdx.x * kRssWaves + wave) * kGroups + g;
   const int m = arr < count ? n : 0;
   K* gk = keys + (arr < count ? arr * stride : 0);
-  rss_group_sort<F, K, false, G>(lds[wave * kGroups + g], gk, nullptr, m, flip, k0);
+  rss_group_sort<F, K, false, G>(lds[wave * kGroups + g], gk, nullptr, m, flip, k0, level_cap);
 }
 
 template <int F, class K, int G>
 static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, K flip, int k0,
-                               hipStream_t s) {
+                               int level_cap, hipStream_t s) {
   constexpr int per_block = kRssWaves * (kWave / G);
   const int64_t blocks = (count + per_block - 1) / per_block;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL((rss_fixed_kernel<F, K, G>), dim3((unsigned)blocks), dim3(kRssThreads), 0, s, keys, n,
-                     count, stride, flip, k0);
+                     count, stride, flip, k0, level_cap);
   return hipGetLastError();
 }
 
 template <int F, class K>
 static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
   const Tuning t = tuning();
-  if (n <= 64) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], s);
-  if (n <= 128) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], s);
-  return launch_rss_g<F, K, 64>(keys, n, count, stride, flip, t.rss_k[2], s);
+  if (n <= 64) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], t.rss_level_cap, s);
+  if (n <= 128) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], t.rss_level_cap, s);
+  return launch_rss_g<F, K, 64>(keys, n, count, stride, flip, t.rss_k[2], t.rss_level_cap, s);
 }
 
 hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,

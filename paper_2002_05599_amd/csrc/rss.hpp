@@ -17,9 +17,9 @@
 //   3. classify: bucket j = #{splitters < e}, i.e. s_j < e <= s_{j+1}, found
 //      by descending the perfect splitter tree without branches: compare with
 //      the root, then keep either the left or the right subtree with selects
-//      (the paper's "unconditional copy of the left subtree, conditionally
-//      overwritten with the right one"), and append the comparison bit to the
-//      bucket index, j = 2j + [e > root].  The first level holds a narrow
+//      (Section 3 copies one subtree and replaces it by the other only when
+//      the comparison says so), and append the comparison bit to the bucket
+//      index, j = 2j + [e > root].  The first level holds a narrow
 //      tree (at most 32 bytes of splitters) in registers; wider trees and
 //      later levels, whose lanes work on different buckets, search the
 //      bucket's sorted sample in LDS with the same branch-free steps;
@@ -40,9 +40,10 @@
 // {e < v}, {e == v}, {e > v}; the middle part is already in final order.  Every
 // other split sends the smallest splitter's key to bucket 0 and the largest
 // splitter's key above it, so every child is strictly smaller than its parent.
-// After kLevelCap levels any remaining pending bucket is finished by a
-// rank-counting sort (each key's final position is the number of keys that
-// must precede it), which is always correct.
+// After a cap of levels (kLevelCap, or fewer when tuned down) any remaining
+// pending bucket is finished by a rank-counting sort (each key's final
+// position is the number of keys that must precede it), which is always
+// correct.
 #pragma once
 
 #include "common.hpp"
@@ -479,9 +480,10 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
 
 // Sorts the array of m keys (0 <= m <= 4G) that the group holds in L.key (and
 // L.val), in place in LDS.  Every lane of the wave must call this (loops are
-// wave-uniform).
+// wave-uniform).  k0: first-level bucket count; level_cap (1..kLevelCap):
+// levels of sample sort before the rank-counting fallback.
 template <int F, class K, bool V, int G>
-__device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0) {
+__device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0, int level_cap) {
   const int gl = lane_id() % G;
   int np = m > 16 ? 1 : 0;
   int nf = (m >= 2 && m <= 16) ? 1 : 0;
@@ -496,7 +498,7 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
 
   int cur = 0;
   for (int level = 0; ballot(np > 0) != 0ull; ++level) {
-    if (level == kLevelCap) {
+    if (level == level_cap) {
       rank_sort_pending(L, cur, np);
       break;
     }
@@ -580,10 +582,11 @@ __device__ __forceinline__ void rss_group_store(GroupLds<K, V, G>& L, K* gk, uin
 // the group's array in global memory; keys are XORed with flip on load and
 // store.
 template <int F, class K, bool V, int G>
-__device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip, int k0) {
+__device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip, int k0,
+                                               int level_cap) {
   rss_group_load(L, gk, gv, m, flip);
   wave_lds_sync();
-  rss_group_sort_lds<F>(L, m, k0);
+  rss_group_sort_lds<F>(L, m, k0, level_cap);
   rss_group_store(L, gk, gv, m, flip);
   wave_lds_sync();
 }

@@ -2,8 +2,8 @@
 // keys[offsets[i], offsets[i+1]), sizes 0..256, with an optional uint32
 // payload permuted with the keys.
 //
-// The paper's future-work proposal (Section 5) is to bucket the base cases by
-// size and solve batches of subproblems of identical size.  That is what
+// Section 5 proposes, as future work, to group the base cases by their size
+// and to sort each group of equally sized subproblems together.  That is what
 // happens here, entirely on the device:
 //
 //   count    each block histograms the size classes of its segments
@@ -241,7 +241,8 @@ template <class K, bool V> struct WaveLds {
 template <int F, class K, bool V, int G>
 __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint32_t* vals,
                                          const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
-                                         int list, int count, int first, int rounds, K flip, int k0) {
+                                         int list, int count, int first, int rounds, K flip, int k0,
+                                         int level_cap) {
   constexpr int kGroups = kWave / G;
   auto* L = reinterpret_cast<GroupLds<K, V, G>*>(wave_lds);
   const int lane = lane_id();
@@ -296,7 +297,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
       bounds(r + 1, lo_n, m_n);
       fetch(lo_n, m_n);
     }
-    rss_group_sort_lds<F>(L[g], m, k0);
+    rss_group_sort_lds<F>(L[g], m, k0, level_cap);
     rss_group_store(L[g], keys + lo, V ? vals + lo : nullptr, m, flip);
     wave_lds_sync();
     lo = lo_n;
@@ -313,6 +314,7 @@ struct SortArgs {
   int k0[3];
   int interleave;  // alternate RSS and network tiles in the persistent kernel
   int net_mix;     // class 0 holds every network size, in batch order
+  int level_cap;   // RSS levels before the rank-counting fallback
 };
 
 // Kind sets of the persistent kernels: every class (one kernel holding every
@@ -348,15 +350,18 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint3
   }
   if constexpr (KS == kKindAll || KS == kKindRss16) {
     if (c == 15)
-      rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0]);
+      rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0],
+                            a.level_cap);
   }
   if constexpr (KS == kKindAll || KS == kKindRss32) {
     if (c == 16)
-      rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1]);
+      rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1],
+                            a.level_cap);
   }
   if constexpr (KS == kKindAll || KS == kKindRss64) {
     if (c == 17)
-      rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2]);
+      rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2],
+                            a.level_cap);
   }
 }
 
@@ -463,7 +468,8 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
     const int list = (int)a.ctrl[kCtrlStart + kClass];
     const int k0 = a.k0[KS - kKindRss16];
     auto run_units = [&](int u, int n) {
-      rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0);
+      rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0,
+                           a.level_cap);
     };
     const int units = (count + kGroups - 1) / kGroups;
     const int R = class_rounds(kClass, count, a.rounds, waves, kPersistTpw);
@@ -566,13 +572,13 @@ seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, 
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
   } else if constexpr (KIND == 1) {
     rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[0]);
+                          a.k0[0], a.level_cap);
   } else if constexpr (KIND == 2) {
     rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[1]);
+                          a.k0[1], a.level_cap);
   } else {
     rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[2]);
+                          a.k0[2], a.level_cap);
   }
 }
 
@@ -600,8 +606,9 @@ struct SegmentedCache {
 // Working memory of the stream `s` on this device (created on first use; calls
 // on different streams never share it, so they may overlap on the device).
 SegmentedCache* workspace_for(DeviceCtx* c, hipStream_t s);
-// Grows the workspace's segment-id list to hold nseg ids (caller holds ws->mu).
-hipError_t ensure_workspace(SegmentedCache* ws, int32_t nseg);
+// Grows the workspace's segment-id list to hold nseg ids, stream-ordered on
+// `s` (caller holds ws->mu).
+hipError_t ensure_workspace(SegmentedCache* ws, int32_t nseg, hipStream_t s);
 
 template <int F, class K, bool V, int KS>
 static int persistent_blocks(DeviceCtx* c) {
@@ -631,6 +638,7 @@ inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
   a.k0[2] = t.rss_k[2];
   a.interleave = t.interleave;
   a.net_mix = t.net_mix;
+  a.level_cap = t.rss_level_cap;
   return a;
 }
 
@@ -864,7 +872,7 @@ static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* o
   SegmentedCache* ws = workspace_for(c, s);
   if (!ws) return -5;
   std::lock_guard<std::mutex> lock(ws->mu);
-  hipError_t e = ensure_workspace(ws, nseg);
+  hipError_t e = ensure_workspace(ws, nseg, s);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? -5 : -4;
   const bool fam = tuning().family == 1;
   if (vals)

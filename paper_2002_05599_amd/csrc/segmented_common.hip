@@ -122,20 +122,23 @@ SegmentedCache* workspace_for(DeviceCtx* c, hipStream_t s) {
   return ws;
 }
 
-hipError_t ensure_workspace(SegmentedCache* s, int32_t nseg) {
+hipError_t ensure_workspace(SegmentedCache* s, int32_t nseg, hipStream_t stream) {
+  if (s->ids_cap >= nseg) return hipSuccess;
+  // Growing, ordered on the workspace's own stream (the only stream that uses
+  // it): the old list is released after the work already queued there, and
+  // the new one is ready for the work queued next.  No host or device sync.
   hipError_t e = hipSuccess;
-  if (s->ids_cap < nseg) {
-    // growing: wait for in-flight users of the old list before freeing it
-    e = hipDeviceSynchronize();
-    if (e == hipSuccess && s->ids) e = hipFree(s->ids);
+  if (s->ids) e = hipFreeAsync(s->ids, stream);
+  s->ids = nullptr;
+  s->ids_cap = 0;
+  int64_t cap = nseg < 1024 ? 1024 : (int64_t)nseg + nseg / 4;
+  if (cap > 0x7FFFFFFF) cap = 0x7FFFFFFF;
+  if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&s->ids), cap * sizeof(int32_t), stream);
+  if (e != hipSuccess) {
     s->ids = nullptr;
-    s->ids_cap = 0;
-    int64_t cap = nseg < 1024 ? 1024 : (int64_t)nseg + nseg / 4;
-    if (cap > 0x7FFFFFFF) cap = 0x7FFFFFFF;
-    if (e == hipSuccess) e = hipMalloc(&s->ids, cap * sizeof(int32_t));
-    if (e != hipSuccess) return e;
-    s->ids_cap = cap;
+    return e;
   }
+  s->ids_cap = cap;
   return hipSuccess;
 }
 

@@ -1,11 +1,32 @@
 import os
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+# every tuning knob the library exposes (include/smallsort.h)
+TUNING_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "persist_occ", "rss_rounds",
+                "interleave", "persist_split", "net_mix", "rss_level_cap", "large_base")
 
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI library)")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _restore_tuning():
+    """Tests that change tuning knobs must not leak them into later modules:
+    snapshot every knob before a module and restore it afterwards."""
+    import paper_2002_05599_amd as ss
+    if not os.path.exists(ss.lib_path()):
+        yield
+        return
+    before = {k: ss.get_tuning(k) for k in TUNING_KNOBS}
+    yield
+    for k, v in before.items():
+        if v >= 0 and ss.get_tuning(k) != v:
+            ss.set_tuning(k, v)

@@ -42,3 +42,23 @@ def pairs_multiset_equal(k1, v1, k2, v2, offsets):
         if a != b:
             return i
     return None
+
+
+class tuned:
+    """Context manager: set tuning knobs, restore them on exit."""
+
+    def __init__(self, **knobs):
+        self.knobs = knobs
+
+    def __enter__(self):
+        import paper_2002_05599_amd as ss
+        self.old = {k: ss.get_tuning(k) for k in self.knobs}
+        for k, v in self.knobs.items():
+            ss.set_tuning(k, v)
+        return self
+
+    def __exit__(self, *exc):
+        import paper_2002_05599_amd as ss
+        for k, v in self.old.items():
+            ss.set_tuning(k, v)
+        return False

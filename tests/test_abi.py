@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     for want in ["sort_small_u32", "sort_small_i32", "sort_small_u64", "sort_small_i64",
                  "segmented_sort_u32", "segmented_sort_i32", "segmented_sort_u64", "segmented_sort_i64",
                  "ss_segmented_sort", "ss_device_status", "ss_strerror", "ss_load_tuning",
-                 "ss_set_tuning_value", "ss_get_tuning_value", "ss_version"]:
+                 "ss_set_tuning_value", "ss_get_tuning_value", "ss_version", "ss_stream_copy"]:
         assert want in names
 
 
@@ -66,10 +66,16 @@ def test_argument_errors_need_no_device(lib):
     assert lib.ss_segmented_sort(0, p, None, p, 1, 9, None) == -1
     assert lib.ss_segmented_sort(2, ctypes.c_void_p(0x1004), None, p, 1, 0, None) == -2
     assert lib.ss_device_status(None, None) == -1
+    assert lib.ss_stream_copy(p, p, -16, None) == -1
+    assert lib.ss_stream_copy(None, None, 0, None) == 0
+    assert lib.ss_stream_copy(None, p, 16, None) == -1
+    assert lib.ss_stream_copy(p, ctypes.c_void_p(0x1008), 16, None) == -2
+    assert lib.ss_stream_copy(p, p, 24, None) == -2
 
 
 def test_tuning_roundtrip(lib, tmp_path):
     old = ss.get_tuning("rss_k_small")
+    old_family = ss.get_tuning("family")
     ss.set_tuning("rss_k_small", 8)
     assert ss.get_tuning("rss_k_small") == 8
     with pytest.raises(ss.SmallSortError):
@@ -95,5 +101,12 @@ def test_tuning_roundtrip(lib, tmp_path):
     f.write_text('{"rss_k_small": 4, ')
     with pytest.raises(ss.SmallSortError):
         ss.load_tuning(str(f))
-    ss.set_tuning("family", 0)
+    ss.set_tuning("family", old_family)
     ss.set_tuning("rss_k_small", old)
+    old_cap = ss.get_tuning("rss_level_cap")
+    for bad in (0, 9):
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning("rss_level_cap", bad)
+    ss.set_tuning("rss_level_cap", 1)
+    assert ss.get_tuning("rss_level_cap") == 1
+    ss.set_tuning("rss_level_cap", old_cap)

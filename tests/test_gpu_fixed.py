@@ -8,7 +8,7 @@ import pytest
 import oracle
 import paper_2002_05599_amd as ss
 from paper_2002_05599_amd import inputs
-from helpers import first_mismatch, from_dev, to_dev
+from helpers import first_mismatch, from_dev, to_dev, tuned
 
 pytestmark = pytest.mark.gpu
 
@@ -30,28 +30,40 @@ def run_fixed(keys_np, n, count, stride):
     return from_dev(t)
 
 
+FAMILIES = [0, 1]
+
+
+@pytest.mark.parametrize("family", FAMILIES, ids=lambda f: f"family{f}")
 @pytest.mark.parametrize("dtype", TYPES, ids=lambda d: np.dtype(d).name)
 @pytest.mark.parametrize("n", range(2, 17))
-def test_networks_match_oracle_all_distributions(n, dtype):
+def test_networks_match_oracle_all_distributions(n, dtype, family):
     # several 256-array tiles plus a ragged tail
     count = 3 * 256 + 37
-    for k, dist in enumerate(inputs.DISTRIBUTIONS):
-        a = inputs.fixed_keys(dtype, n, count, dist, seed=100 + 7 * n + k)
-        got = run_fixed(a, n, count, n)
-        want = oracle.sort_fixed(a, n, count, n)
-        assert (got == want).all(), f"{dist}: {first_mismatch(got, want, n)}"
+    with tuned(family=family):
+        for k, dist in enumerate(inputs.DISTRIBUTIONS):
+            a = inputs.fixed_keys(dtype, n, count, dist, seed=100 + 7 * n + k)
+            got = run_fixed(a, n, count, n)
+            want = oracle.sort_fixed(a, n, count, n)
+            assert (got == want).all(), f"{dist}: {first_mismatch(got, want, n)}"
+        # the direct (unstaged) kernel: a stride other than n
+        a = inputs.fixed_keys(dtype, n, 300, "uniform", seed=n)
+        a = np.concatenate([a.reshape(300, n), a.reshape(300, n)[:, :1]], axis=1).reshape(-1)
+        got = run_fixed(a, n, 300, n + 1)
+        assert (got == oracle.sort_fixed(a, n, 300, n + 1)).all()
 
 
+@pytest.mark.parametrize("family", FAMILIES, ids=lambda f: f"family{f}")
 @pytest.mark.parametrize("dtype", [np.uint32, np.uint64, np.int32], ids=lambda d: np.dtype(d).name)
 @pytest.mark.parametrize("n", range(2, 17))
-def test_zero_one_principle_on_device(n, dtype):
+def test_zero_one_principle_on_device(n, dtype, family):
     """Every 0/1 input of length n (2^n arrays) comes out sorted (0-1 principle)."""
     x = np.arange(1 << n, dtype=np.uint64)
     bits = ((x[:, None] >> np.arange(n, dtype=np.uint64)) & np.uint64(1)).astype(np.int64)
     info = np.iinfo(dtype)
     lo, hi = (info.min, info.max)  # the extremes stand for 0 and 1
     a = np.where(bits == 1, hi, lo).astype(dtype).reshape(-1)
-    got = run_fixed(a, n, 1 << n, n).reshape(-1, n)
+    with tuned(family=family):
+        got = run_fixed(a, n, 1 << n, n).reshape(-1, n)
     ones = bits.sum(axis=1)
     want = np.where(np.arange(n)[None, :] >= (n - ones)[:, None], hi, lo).astype(dtype)
     assert (got == want).all()

@@ -117,3 +117,55 @@ def test_rss_stride_and_repeat():
     got = run_fixed(a, n, count, stride)
     assert (got == oracle.sort_fixed(a, n, count, stride)).all()
     assert (run_fixed(a, n, count, stride) == got).all()
+
+
+@pytest.mark.parametrize("cap", [1, 2])
+@pytest.mark.parametrize("kind", ["uniform", "zipf", "two_values", "max_heavy", "one_big_dup"])
+def test_rss_level_cap_fallback_fixed(cap, kind):
+    """Register Sample Sort stopped after `cap` levels: every bucket still above
+    16 keys goes through the rank-counting fallback.  With a first level of 4
+    buckets, arrays of 65..256 keys always leave such buckets, so the fallback
+    runs on every array of those sizes."""
+    from helpers import tuned
+    with tuned(rss_level_cap=cap, rss_k_small=4, rss_k_mid=4, rss_k_large=4):
+        for dtype in (np.uint32, np.int64):
+            for n in (17, 40, 64, 100, 128, 200, 256):
+                count = 37
+                if kind == "uniform":
+                    a = inputs.fixed_keys(dtype, n, count, "uniform", seed=3 * n + cap)
+                else:
+                    a = special(dtype, n, count, kind, seed=n + cap)
+                got = run_fixed(a, n, count, n)
+                want = oracle.sort_fixed(a, n, count, n)
+                assert (got == want).all(), (cap, kind, n, first_mismatch(got, want, n))
+
+
+@pytest.mark.parametrize("cap", [1, 2])
+@pytest.mark.parametrize("mode", [ss.MODE_AUTO, ss.MODE_PLAIN], ids=["graph", "plain"])
+def test_rss_level_cap_fallback_segmented_payload(cap, mode):
+    """The fallback carries payloads: distinct keys (payload exact) and
+    duplicate-heavy keys (keys exact, payload a per-segment permutation), with
+    both first-level widths (narrow forces the fallback, wide rarely needs it)."""
+    from helpers import pairs_multiset_equal, tuned
+    sizes = np.random.default_rng(cap).integers(17, 257, size=1500)
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    for k in (4, 16):
+        with tuned(rss_level_cap=cap, rss_k_small=k, rss_k_mid=k, rss_k_large=k):
+            keys = inputs.distinct_u64(total, seed=cap + k)
+            vals = inputs.segment_index_payload(off)
+            tk, tv, to = to_dev(keys), to_dev(vals), to_dev(off)
+            ss.segmented_sort(tk, to, tv, mode=mode)
+            gk, gv = from_dev(tk), from_dev(tv)
+            wk, wv = oracle.sort_segments(keys, off, vals)
+            assert (gk == wk).all(), first_mismatch(gk, wk)
+            assert (gv == wv).all(), first_mismatch(gv, wv)
+            dup = (inputs.random_keys(np.uint32, total, seed=k) % 3).astype(np.uint32)
+            dup[np.random.default_rng(k).random(total) < 0.2] = np.iinfo(np.uint32).max
+            vals = np.arange(total, dtype=np.uint32)
+            tk, tv = to_dev(dup), to_dev(vals)
+            ss.segmented_sort(tk, to, tv, mode=mode)
+            gk, gv = from_dev(tk), from_dev(tv)
+            wk, _ = oracle.sort_segments(dup, off)
+            assert (gk == wk).all(), first_mismatch(gk, wk)
+            assert pairs_multiset_equal(gk, gv, dup, vals, off) is None

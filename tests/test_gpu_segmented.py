@@ -253,3 +253,113 @@ def test_mixed_size_network_tiles(dtype, mode):
         assert ss.device_status() == 0
     finally:
         ss.set_tuning("net_mix", old)
+
+
+def test_graph_replays_back_to_back_without_sync():
+    """Several calls of the cached graph queued on one stream, each on its own
+    buffers with its own segment count, with no host synchronisation between
+    them (as the bench issues them): every output must match the oracle."""
+    import torch
+    cases = []
+    for rep, nseg in enumerate([3000, 800, 12000, 5, 4000, 1]):
+        keys, vals, off = inputs.config4(nseg=nseg, seed=60 + rep)
+        cases.append((keys, vals, off, to_dev(keys), to_dev(vals), to_dev(off)))
+    torch.cuda.synchronize()
+    for _, _, _, tk, tv, to in cases:
+        ss.segmented_sort(tk, to, tv, mode=ss.MODE_AUTO)
+    torch.cuda.synchronize()
+    for rep, (keys, vals, off, tk, tv, _) in enumerate(cases):
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (tk.cpu().numpy() == wk).all() and (tv.cpu().numpy() == wv).all(), rep
+    assert ss.device_status() == 0
+
+
+KERNEL_FORMS = [dict(persist_split=s, interleave=i, net_mix=m) for s in (0, 1) for i in (0, 1) for m in (0, 1)
+                if not (s == 1 and i == 1)]  # interleaving only applies to the single kernel
+
+
+@pytest.mark.parametrize("form", KERNEL_FORMS,
+                         ids=lambda f: f"split{f['persist_split']}-il{f['interleave']}-mix{f['net_mix']}")
+@pytest.mark.parametrize("mode", [ss.MODE_AUTO, ss.MODE_PERSISTENT], ids=["graph", "persistent"])
+def test_persistent_kernel_forms(form, mode):
+    """Every persistent kernel layout the autotuner may choose: one kernel for all
+    classes (with and without interleaving) or one per kind, per-size or mixed
+    network tiles.  Mixed sizes with RSS segments, keys-only duplicates and
+    distinct 64-bit keys with payload."""
+    from helpers import tuned
+    rng = np.random.default_rng(17)
+    sizes = np.concatenate([rng.integers(0, 257, size=2500), rng.integers(0, 17, size=6000),
+                            rng.integers(17, 65, size=1500)])
+    rng.shuffle(sizes)
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    with tuned(**form):
+        for dtype in (np.uint32, np.int64):
+            keys = inputs.random_keys(dtype, total, seed=18)
+            keys[rng.random(total) < 0.3] = 7
+            got, _ = run_seg(keys, off, mode=mode)
+            want, _ = oracle.sort_segments(keys, off)
+            assert (got == want).all(), (dtype, first_mismatch(got, want))
+        keys = inputs.distinct_u64(total, seed=19)
+        vals = inputs.segment_index_payload(off)
+        gk, gv = run_seg(keys, off, vals, mode=mode)
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (gk == wk).all() and (gv == wv).all()
+        assert ss.device_status() == 0
+
+
+@pytest.mark.parametrize("family", [0, 1])
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_network_families_segmented(family, mode):
+    """Both network families in the segmented network tiles and RSS finishing."""
+    from helpers import tuned
+    with tuned(family=family):
+        sizes = inputs.geometric_sizes(20000, seed=21)
+        off = inputs.offsets_from_sizes(sizes)
+        total = int(off[-1])
+        keys = inputs.distinct_u64(total, seed=22)
+        vals = inputs.segment_index_payload(off)
+        gk, gv = run_seg(keys, off, vals, mode=mode)
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (gk == wk).all() and (gv == wv).all()
+        k32 = inputs.random_keys(np.int32, total, seed=23)
+        got, _ = run_seg(k32, off, mode=mode)
+        want, _ = oracle.sort_segments(k32, off)
+        assert (got == want).all(), first_mismatch(got, want)
+
+
+def test_workspace_grows_while_another_stream_runs():
+    """Stream A's working memory grows (stream-ordered) while a large batch on
+    stream B is still in flight: both results must match the oracle."""
+    import torch
+    sa = torch.cuda.Stream()
+    sb = torch.cuda.Stream()
+    kb, vb, ob = inputs.config4(nseg=400_000, seed=31)
+    tb = (to_dev(kb), to_dev(vb), to_dev(ob))
+    small = inputs.config4(nseg=100, seed=32)
+    big = inputs.config4(nseg=300_000, seed=33)
+    ta_small = tuple(to_dev(x) for x in small)
+    ta_big = tuple(to_dev(x) for x in big)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sa):
+        ss.segmented_sort(ta_small[0], ta_small[2], ta_small[1])  # A's workspace sized for 100 segments
+    with torch.cuda.stream(sb):
+        ss.segmented_sort(tb[0], tb[2], tb[1])                    # B busy with a large batch
+    with torch.cuda.stream(sa):
+        ss.segmented_sort(ta_big[0], ta_big[2], ta_big[1])        # A grows while B runs
+    torch.cuda.synchronize()
+    for (k, v, o), (tk, tv, _) in ((small, ta_small), (big, ta_big), ((kb, vb, ob), tb)):
+        wk, wv = oracle.sort_segments(k, o, v)
+        assert (tk.cpu().numpy() == wk).all() and (tv.cpu().numpy() == wv).all()
+    assert ss.device_status() == 0
+
+
+def test_stream_copy_probe():
+    """The bandwidth probe copies bytes exactly and rejects misaligned sizes."""
+    import torch
+    src = torch.from_numpy(inputs.random_keys(np.uint32, (1 << 20) + 64, seed=3)).cuda()
+    dst = torch.zeros_like(src)
+    ss.stream_copy(dst, src)
+    assert torch.equal(dst, src)
+    with pytest.raises(ss.SmallSortError):
+        ss.stream_copy(dst[1:], src[1:])
