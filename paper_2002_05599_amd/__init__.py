@@ -71,7 +71,13 @@ def lib() -> ctypes.CDLL:
                 raise RuntimeError(
                     f"{path} not found: build it with `python -m paper_2002_05599_amd.build` "
                     "(or __graft_entry__.build()); there is no non-GPU fallback")
+            # torch first: it maps the HIP runtime it bundles, whose soname
+            # the library's dependency then resolves to.  Loaded the other way
+            # round, the process would hold two HIP runtimes and torch's
+            # streams would be foreign handles to the library's runtime.
+            import torch  # noqa: F401
             handle = ctypes.CDLL(path)
+            _check_one_hip_runtime()
             for name, (res, args) in _SIGS.items():
                 f = getattr(handle, name)
                 f.restype = res
@@ -79,6 +85,18 @@ def lib() -> ctypes.CDLL:
             _lib = handle
             _autoload_tuning(handle)
     return _lib
+
+
+def _check_one_hip_runtime():
+    """Raise if two different HIP runtimes are mapped into the process."""
+    try:
+        maps = open("/proc/self/maps").read().splitlines()
+    except OSError:
+        return
+    paths = {os.path.realpath(ln.split()[-1]) for ln in maps if "libamdhip64" in ln and "/" in ln}
+    if len(paths) > 1:
+        raise RuntimeError("two HIP runtimes are loaded (" + ", ".join(sorted(paths)) + "); import torch "
+                           "before anything loads libamdhip64 so that one runtime serves both")
 
 
 def tuning_path() -> str:

@@ -110,3 +110,16 @@ def test_tuning_roundtrip(lib, tmp_path):
     ss.set_tuning("rss_level_cap", 1)
     assert ss.get_tuning("rss_level_cap") == 1
     ss.set_tuning("rss_level_cap", old_cap)
+
+
+def test_binding_maps_one_hip_runtime():
+    """Loading the library before torch is imported must still leave one HIP
+    runtime in the process: torch's streams are handles of that runtime."""
+    import subprocess
+    import sys
+    code = ("import paper_2002_05599_amd as ss; ss.get_tuning('family'); import torch; import os; "
+            "print(len({os.path.realpath(l.split()[-1]) for l in open('/proc/self/maps') "
+            "if 'libamdhip64' in l and '/' in l}))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
