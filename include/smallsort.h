@@ -58,6 +58,7 @@ typedef int32_t ss_status;
 #define SS_EHIP     (-4)  /* a HIP runtime call failed */
 #define SS_ENOMEM   (-5)  /* working memory could not be allocated */
 #define SS_ENOTUNE  (-6)  /* unknown tuning name or unreadable tuning file */
+#define SS_ESCRATCH (-7)  /* batch larger than the no-allocation entry point's scratch */
 
 #define SS_MAX_NETWORK_N 16   /* largest array sorted by a network alone */
 #define SS_MAX_N        256   /* largest array or segment */
@@ -118,6 +119,26 @@ ss_status segmented_sort_i64(int64_t *keys, uint32_t *vals, const int32_t *offse
  */
 ss_status ss_segmented_sort(int32_t key_type, void *keys, uint32_t *vals, const int32_t *offsets,
                             int32_t nseg, int32_t mode, void *stream);
+
+/*
+ * No-allocation form of ss_segmented_sort, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same layout, ownership, results and device status
+ * reporting as ss_segmented_sort with SS_MODE_PERSISTENT; it calls no
+ * hipMalloc, hipFree or other allocating routine.  Its working memory is one
+ * fixed array per device in the library's code object (64 MiB + 80 KiB, held
+ * until the process ends), looked up on the first call on each device.
+ *   nseg: 0..SS_NOALLOC_MAX_SEGMENTS; a larger batch returns SS_ESCRATCH
+ *         before anything is enqueued.
+ * Every call on one device shares that array: calls that overlap on the
+ * device (calls on different streams, or from different host threads, not
+ * ordered by the caller) race and give undefined results.  Calls ordered on
+ * one stream are safe; nothing carries over from one call to the next.
+ * Errors: as ss_segmented_sort, plus SS_ESCRATCH.
+ */
+#define SS_NOALLOC_MAX_SEGMENTS (1 << 24)
+ss_status ss_segmented_sort_noalloc(int32_t key_type, void *keys, uint32_t *vals, const int32_t *offsets,
+                                    int32_t nseg, void *stream);
 
 /*
  * Reads the current device's status word after synchronising `stream`, stores

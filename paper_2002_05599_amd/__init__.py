@@ -17,7 +17,8 @@ import threading
 __all__ = [
     "SmallSortError", "lib", "lib_path", "sort_small", "segmented_sort", "device_status",
     "set_tuning", "get_tuning", "load_tuning", "tuning_path", "version", "KEY_CODES",
-    "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN", "stream_copy",
+    "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN", "stream_copy", "segmented_sort_noalloc",
+    "NOALLOC_MAX_SEGMENTS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,7 +43,10 @@ _SIGS = {
     "ss_load_tuning": (ctypes.c_int32, [ctypes.c_char_p]),
     "ss_version": (ctypes.c_char_p, []),
     "ss_stream_copy": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P]),
+    "ss_segmented_sort_noalloc": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P]),
 }
+
+NOALLOC_MAX_SEGMENTS = 1 << 24  # SS_NOALLOC_MAX_SEGMENTS
 
 _lock = threading.Lock()
 _lib = None
@@ -193,6 +197,28 @@ def segmented_sort(keys, offsets, vals=None, mode=MODE_AUTO, stream=None):
                                  ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), int(mode),
                                  _stream_ptr(stream))
     _check(st, "ss_segmented_sort")
+    return keys, vals
+
+
+def segmented_sort_noalloc(keys, offsets, vals=None, stream=None):
+    """``segmented_sort`` through the entry point that allocates no device
+    memory (fixed per-device scratch; at most NOALLOC_MAX_SEGMENTS segments;
+    calls that overlap on one device race)."""
+    _require_cuda(keys, "keys")
+    _require_cuda(offsets, "offsets")
+    name = _dtype_name(keys)
+    if str(offsets.dtype) != "torch.int32":
+        raise TypeError("offsets must be int32")
+    nseg = offsets.numel() - 1
+    vptr = None
+    if vals is not None:
+        _require_cuda(vals, "vals")
+        if str(vals.dtype) != "torch.uint32" or vals.numel() != keys.numel():
+            raise TypeError("vals must be a uint32 tensor shaped like keys")
+        vptr = ctypes.c_void_p(vals.data_ptr())
+    st = lib().ss_segmented_sort_noalloc(KEY_CODES[name], ctypes.c_void_p(keys.data_ptr()), vptr,
+                                         ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), _stream_ptr(stream))
+    _check(st, "ss_segmented_sort_noalloc")
     return keys, vals
 
 

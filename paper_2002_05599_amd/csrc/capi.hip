@@ -27,6 +27,10 @@ Tuning tuning() {
 static std::mutex g_ctx_mu;
 static std::vector<DeviceCtx*> g_ctx;
 
+// The status word of each device: a device global (zero when the code object
+// is loaded), so that setting up a device allocates no memory.
+static __device__ int g_status_word;
+
 DeviceCtx* device_ctx(hipError_t* err) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -40,11 +44,9 @@ DeviceCtx* device_ctx(hipError_t* err) {
   DeviceCtx* c = new DeviceCtx();
   c->device = dev;
   e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipMalloc(&c->status, sizeof(int));
-  if (e == hipSuccess) e = hipMemset(c->status, 0, sizeof(int));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  // this device's copy of the status word (its address differs per device)
+  if (e == hipSuccess) e = hipGetSymbolAddress(reinterpret_cast<void**>(&c->status), HIP_SYMBOL(g_status_word));
   if (e != hipSuccess) {
-    if (c->status) (void)hipFree(c->status);
     delete c;
     *err = e;
     return nullptr;
@@ -119,6 +121,40 @@ static ss_status segmented(int32_t key_type, void* keys, uint32_t* vals, const i
     default:
       return segmented_u64(c, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0x8000000000000000ull,
                            mode, s);
+  }
+}
+
+// The no-allocation form of `segmented`: same checks, then the binning and
+// persistent kernels launched directly on the device's fixed scratch array.
+static_assert(kNoAllocMaxSeg == SS_NOALLOC_MAX_SEGMENTS, "header and library agree on the scratch limit");
+
+static ss_status segmented_noalloc(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
+                                   int32_t nseg, hipStream_t s) {
+  if (key_type < SS_KEY_U32 || key_type > SS_KEY_I64) return SS_EINVAL;
+  if (nseg < 0) return SS_EINVAL;
+  if (nseg > kNoAllocMaxSeg) return SS_ESCRATCH;
+  if (nseg == 0) return SS_OK;
+  if (keys == nullptr || offsets == nullptr) return SS_EINVAL;
+  const size_t ksz = (key_type == SS_KEY_U32 || key_type == SS_KEY_I32) ? 4 : 8;
+  if (reinterpret_cast<uintptr_t>(keys) % ksz != 0) return SS_EALIGN;
+  if (reinterpret_cast<uintptr_t>(offsets) % 4 != 0) return SS_EALIGN;
+  if (vals && reinterpret_cast<uintptr_t>(vals) % 4 != 0) return SS_EALIGN;
+  hipError_t herr = hipSuccess;
+  DeviceCtx* c = device_ctx(&herr);
+  if (!c) return from_hip(herr);
+  SegBuffers b;
+  herr = noalloc_buffers(c, &b);
+  if (herr != hipSuccess) return from_hip(herr);
+  switch (key_type) {
+    case SS_KEY_U32:
+      return segmented_direct_u32(c, b, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0u, s);
+    case SS_KEY_I32:
+      return segmented_direct_u32(c, b, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0x80000000u, s);
+    case SS_KEY_U64:
+      return segmented_direct_u64(c, b, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0ull, s);
+    default:
+      return segmented_direct_u64(c, b, static_cast<uint64_t*>(keys), vals, offsets, nseg,
+                                  0x8000000000000000ull, s);
   }
 }
 
@@ -204,6 +240,11 @@ ss_status ss_segmented_sort(int32_t key_type, void* keys, uint32_t* vals, const 
   return segmented(key_type, keys, vals, offsets, nseg, mode, static_cast<hipStream_t>(stream));
 }
 
+ss_status ss_segmented_sort_noalloc(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
+                                    int32_t nseg, void* stream) {
+  return segmented_noalloc(key_type, keys, vals, offsets, nseg, static_cast<hipStream_t>(stream));
+}
+
 ss_status ss_device_status(void* stream, int32_t* out) {
   if (!out) return SS_EINVAL;
   hipError_t herr = hipSuccess;
@@ -229,6 +270,7 @@ const char* ss_strerror(ss_status status) {
     case SS_EHIP: return "HIP runtime error";
     case SS_ENOMEM: return "out of device memory";
     case SS_ENOTUNE: return "unknown tuning parameter or unreadable tuning file";
+    case SS_ESCRATCH: return "batch exceeds the fixed working memory of the no-allocation entry point";
     default: return "unknown status";
   }
 }

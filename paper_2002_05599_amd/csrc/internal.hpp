@@ -43,7 +43,24 @@ struct DeviceCtx {
   int num_cus = 0;
   int* status = nullptr;       // device int32 status word
   SegRegistry* seg = nullptr;  // segmented-path workspaces, one per stream
+  void* scratch = nullptr;     // this device's address of the fixed no-allocation scratch array
 };
+
+// Device working memory of one segmented call: the segment-id list grouped by
+// size class, the control block (class counts, class starts, claim counters)
+// and the per-block class histogram of the binning.
+struct SegBuffers {
+  int32_t* ids = nullptr;
+  uint32_t* ctrl = nullptr;
+  uint32_t* blockhist = nullptr;
+};
+
+// Largest batch of the no-allocation segmented entry point (its segment-id
+// list lives in the fixed scratch array).
+constexpr int32_t kNoAllocMaxSeg = 1 << 24;
+// The scratch array carved into SegBuffers for `nseg` <= kNoAllocMaxSeg
+// segments; the device address is looked up once per device (hipGetSymbolAddress).
+hipError_t noalloc_buffers(DeviceCtx* c, SegBuffers* out);
 // Context of the current device, created on first use; nullptr on failure
 // with *err set to a HIP error.
 DeviceCtx* device_ctx(hipError_t* err);
@@ -55,5 +72,11 @@ int segmented_u32(DeviceCtx* c, uint32_t* keys, uint32_t* vals, const int32_t* o
                   uint32_t flip, int mode, hipStream_t s);
 int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
                   uint64_t flip, int mode, hipStream_t s);
+// The same sorts with the persistent kernels launched directly on the given
+// buffers (no graph, no working-memory allocation): the no-allocation path.
+int segmented_direct_u32(DeviceCtx* c, const SegBuffers& b, uint32_t* keys, uint32_t* vals,
+                         const int32_t* offsets, int32_t nseg, uint32_t flip, hipStream_t s);
+int segmented_direct_u64(DeviceCtx* c, const SegBuffers& b, uint64_t* keys, uint32_t* vals,
+                         const int32_t* offsets, int32_t nseg, uint64_t flip, hipStream_t s);
 
 }  // namespace ss

@@ -601,6 +601,13 @@ struct SegmentedCache {
   uint32_t* blockhist = nullptr;
   uint32_t* host_ctrl = nullptr;  // pinned, for the plain baseline
   std::vector<GraphEntry> graphs;
+  SegBuffers buffers() const {
+    SegBuffers b;
+    b.ids = ids;
+    b.ctrl = ctrl;
+    b.blockhist = blockhist;
+    return b;
+  }
 };
 
 // Working memory of the stream `s` on this device (created on first use; calls
@@ -625,12 +632,12 @@ static int persistent_blocks(DeviceCtx* c) {
   return max(occ * c->num_cus, kTileParts);
 }
 
-inline SortArgs make_args(const int32_t* offsets, SegmentedCache* s) {
+inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
   const Tuning t = tuning();
   SortArgs a;
   a.offsets = offsets;
-  a.ids = s->ids;
-  a.ctrl = s->ctrl;
+  a.ids = s.ids;
+  a.ctrl = s.ctrl;
   a.rounds = t.rss_rounds;
   a.waves = 1;
   a.k0[0] = t.rss_k[0];
@@ -677,16 +684,16 @@ struct SegLaunch {
     return (i == 3 && mix) ? kKindNetMix : order[i - 3];
   }
 
-  void fill(DeviceCtx* c, SegmentedCache* s, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
+  void fill(DeviceCtx* c, const SegBuffers& s, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
     offsets = off;
     nseg = n;
-    blockhist = s->blockhist;
+    blockhist = s.blockhist;
     status = c->status;
     nblocks = kBinBlocks;
-    ctrl = s->ctrl;
-    ctrl_c = s->ctrl;
-    blockbase = s->blockhist;
-    ids = s->ids;
+    ctrl = s.ctrl;
+    ctrl_c = s.ctrl;
+    blockbase = s.blockhist;
+    ids = s.ids;
     keys = k;
     vals = v;
     args = make_args(off, s);
@@ -840,9 +847,7 @@ static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream
 }
 
 template <int F, class K, bool V>
-static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets,
-                          int32_t nseg, K flip, int mode, hipStream_t s) {
-  SegLaunch<F, K, V> L;
+static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
   L.split = tuning().persist_split != 0;
   for (int& b : L.persist_blocks) b = 0;
   if (L.split) {
@@ -854,7 +859,14 @@ static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* v
   } else {
     L.persist_blocks[kKindAll] = persistent_blocks<F, K, V, kKindAll>(c);
   }
-  L.fill(c, ws, keys, vals, offsets, nseg, flip);
+}
+
+template <int F, class K, bool V>
+static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets,
+                          int32_t nseg, K flip, int mode, hipStream_t s) {
+  SegLaunch<F, K, V> L;
+  init_launch(c, L);
+  L.fill(c, ws->buffers(), keys, vals, offsets, nseg, flip);
   hipError_t e;
   if (mode == 2)
     e = run_plain(c, ws, L, s);
@@ -880,6 +892,28 @@ static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* o
                : segmented_impl<0, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
   return fam ? segmented_impl<1, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
              : segmented_impl<0, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
+}
+
+// The no-allocation form: binning and persistent kernels launched directly on
+// caller-provided buffers (the fixed scratch array); no graph, no allocation.
+template <int F, class K, bool V>
+static int segmented_direct_impl(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals,
+                                 const int32_t* offsets, int32_t nseg, K flip, hipStream_t s) {
+  SegLaunch<F, K, V> L;
+  init_launch(c, L);
+  L.fill(c, b, keys, vals, offsets, nseg, flip);
+  return L.launch_direct(s) == hipSuccess ? 0 : -4;
+}
+
+template <class K>
+static int segmented_direct_any(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals,
+                                const int32_t* offsets, int32_t nseg, K flip, hipStream_t s) {
+  const bool fam = tuning().family == 1;
+  if (vals)
+    return fam ? segmented_direct_impl<1, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
+               : segmented_direct_impl<0, K, true>(c, b, keys, vals, offsets, nseg, flip, s);
+  return fam ? segmented_direct_impl<1, K, false>(c, b, keys, vals, offsets, nseg, flip, s)
+             : segmented_direct_impl<0, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
 }
 
 }  // namespace ss

@@ -93,6 +93,42 @@ seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint
   }
 }
 
+// --- fixed scratch of the no-allocation entry point ---------------------------
+//
+// One array per device, held from code-object load until the process ends:
+// the control block, the binning histogram and a segment-id list for up to
+// kNoAllocMaxSeg segments (64 MiB + 80 KiB).  Every no-allocation call on a
+// device uses the same array, so such calls must not overlap on one device.
+// Nothing in it needs clearing between calls: the count kernel writes every
+// histogram entry, the scan kernel writes the class counts and starts and
+// zeroes the claim counters, the scatter kernel writes the ids it uses.
+constexpr size_t kScratchCtrlBytes = 8192;
+constexpr size_t kScratchHistBytes = (size_t)kBinBlocks * kClasses * sizeof(uint32_t);
+constexpr size_t kScratchBytes = kScratchCtrlBytes + kScratchHistBytes + (size_t)kNoAllocMaxSeg * sizeof(int32_t);
+static_assert(kCtrlWords * sizeof(uint32_t) <= kScratchCtrlBytes, "control block must fit its scratch slot");
+static_assert(kScratchHistBytes % 256 == 0, "histogram slot keeps the id list 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t noalloc_buffers(DeviceCtx* c, SegBuffers* out) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!c->scratch) {
+    // `scratch` names a host-side stand-in; the device address of this
+    // device's copy comes from the runtime (the caller made c's device current).
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    c->scratch = p;
+  }
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  out->ctrl = reinterpret_cast<uint32_t*>(base);
+  out->blockhist = reinterpret_cast<uint32_t*>(base + kScratchCtrlBytes);
+  out->ids = reinterpret_cast<int32_t*>(base + kScratchCtrlBytes + kScratchHistBytes);
+  return hipSuccess;
+}
+
 struct SegRegistry {
   std::mutex mu;
   std::vector<std::pair<hipStream_t, SegmentedCache*>> list;

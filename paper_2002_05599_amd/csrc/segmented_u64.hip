@@ -8,4 +8,9 @@ int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* o
   return segmented_any<uint64_t>(c, keys, vals, offsets, nseg, flip, mode, s);
 }
 
+int segmented_direct_u64(DeviceCtx* c, const SegBuffers& b, uint64_t* keys, uint32_t* vals, const int32_t* offsets,
+                         int32_t nseg, uint64_t flip, hipStream_t s) {
+  return segmented_direct_any<uint64_t>(c, b, keys, vals, offsets, nseg, flip, s);
+}
+
 }  // namespace ss
