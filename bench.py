@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="all",
                    choices=["all", "fixed16_u32", "copy", "config1", "config2", "rss", "rss_classes", "ragged",
-                            "serve"])
+                            "serve", "is_vs_sn"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extras", action="store_true", help="headline workload only")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -343,6 +343,92 @@ def bench_config2(args):
                         "over 4 buffers", "results": out}
 
 
+def bench_network_vs_insertion(args):
+    """The paper's central comparison (Sections 4.2-4.3, ArrayInRow): for each
+    n = 2..16, the fastest network family against insertion sort ("IS Def",
+    family 2), 2^24 arrays per n, uint32 and int64, uniform and already-sorted
+    rows (insertion sort is adaptive, the networks are not).  Above 16 keys:
+    Register Sample Sort with network and with insertion-sort base cases
+    (Section 4.5) and the IS+SN hybrid (Section 4.6: insertion sort for every
+    array above 16 keys) on the 2^20-array RSS batch."""
+    import torch
+    import paper_2002_05599_amd as ss
+    from paper_2002_05599_amd import inputs
+    count = 1 << 24
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12)
+    fam0 = ss.get_tuning("family")
+    rows = {}
+    try:
+        for dtype, kb in (("u32", 4), ("i64", 8)):
+            for n in range(2, 17):
+                row = {}
+                for dist in ("uniform", "sorted"):
+                    src = device_fixed_keys(torch, dtype, n, count, dist, gen).reshape(-1)
+                    buf = src.clone()
+                    ms = {}
+                    for fam in (0, 1, 2):
+                        ss.set_tuning("family", fam)
+                        # insertion sort is adaptive: every call gets a fresh copy of the
+                        # input (for small n the copy leaves it in the Infinity Cache;
+                        # every variant sees the same, so the ratio stands)
+                        ms[fam] = time_restored(lambda: ss.sort_small(buf, n), lambda: buf.copy_(src), 5)
+                    best_net = min(ms[0], ms[1])
+                    row[dist] = {"best_network_ms": best_net, "best_family": 0 if ms[0] <= ms[1] else 1,
+                                 "insertion_ms": ms[2], "network_speedup": ms[2] / best_net}
+                    del src, buf
+                rows[f"{dtype}_n{n}"] = row
+    finally:
+        ss.set_tuning("family", fam0)
+    torch.cuda.empty_cache()
+    # 17..256 keys: RSS (network base case), RSS with insertion-sort base case, IS+SN
+    keys, off = inputs.config3(nseg=1 << 20, dist="uniform")
+    tk = torch.from_numpy(keys).cuda()
+    to = torch.from_numpy(off).cuda()
+    bufs = StepBuffers((tk,), 3)
+    large = {}
+    for name, knobs in (("rss_network_base", {}), ("rss_insertion_base", {"family": 2}),
+                        ("is_sn_hybrid", {"large_sort": 1})):
+        old = {k: ss.get_tuning(k) for k in knobs}
+        try:
+            for k, v in knobs.items():
+                ss.set_tuning(k, v)
+            ms, _ = time_steps(lambda b: ss.segmented_sort(b[0], to), bufs, 3, 1)
+        finally:
+            for k, v in old.items():
+                ss.set_tuning(k, v)
+        large[name] = {"ms": ms}
+    for name in large:
+        large[name]["speedup_of_rss_network_base"] = large[name]["ms"] / large["rss_network_base"]["ms"]
+    assert ss.device_status() == 0
+    del bufs, tk, to
+    torch.cuda.empty_cache()
+    return {"workload": "networks vs insertion sort: 2^24 arrays per n = 2..16 (u32, i64; uniform and sorted "
+                        "rows); above 16 keys the 2^20-array RSS batch (int32 uniform, graph form)",
+            "per_n": rows, "above_16": large}
+
+
+def time_restored(step, restore, calls, warmup=2):
+    """Median over ``calls`` calls of the event-timed duration of one call,
+    each on a freshly restored input (``restore`` runs untimed before it)."""
+    import torch
+    for _ in range(warmup):
+        restore()
+        step()
+    stream = torch.cuda.current_stream()
+    times = []
+    for _ in range(calls):
+        restore()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        step()
+        ev1.record(stream)
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    return float(np.median(times))
+
+
 def seg_bytes(total, nseg, key_bytes, has_vals):
     return 2 * total * (key_bytes + (4 if has_vals else 0)) + 4 * (nseg + 1)
 
@@ -477,6 +563,7 @@ def compact(x, digits=4):
 EXTRAS = [
     ("config1", bench_config1),
     ("config2", bench_config2),
+    ("network_vs_insertion", bench_network_vs_insertion),
     ("config3_uniform", lambda a: bench_rss(a, "uniform")),
     ("config3_zipf", lambda a: bench_rss(a, "zipf")),
     ("config3_per_class", bench_rss_classes),
@@ -525,6 +612,8 @@ def main():
                "rss_zipf": bench_rss(args, "zipf", steps=args.steps, warmup=args.warmup)}
     elif w == "rss_classes":
         out = bench_rss_classes(args)
+    elif w == "is_vs_sn":
+        out = bench_network_vs_insertion(args)
     elif w == "ragged":
         out = bench_ragged(args, steps=args.steps, warmup=args.warmup)
     else:

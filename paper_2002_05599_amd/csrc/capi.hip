@@ -171,7 +171,7 @@ struct TuneEntry {
 static std::vector<TuneEntry> tune_table() {
   Tuning& t = g_tuning;
   return {
-      {"family", &t.family, 0, 1, false},
+      {"family", &t.family, 0, 2, false},
       {"rss_k_small", &t.rss_k[0], 4, 16, true},
       {"rss_k_mid", &t.rss_k[1], 4, 32, true},
       {"rss_k_large", &t.rss_k[2], 4, 64, true},
@@ -181,6 +181,7 @@ static std::vector<TuneEntry> tune_table() {
       {"persist_split", &t.persist_split, 0, 1, false},
       {"net_mix", &t.net_mix, 0, 1, false},
       {"rss_level_cap", &t.rss_level_cap, 1, 8, false},
+      {"large_sort", &t.large_sort, 0, 1, false},
   };
 }
 

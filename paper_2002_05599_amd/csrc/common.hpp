@@ -75,16 +75,85 @@ template <class K, int N> struct PairOp {
   __device__ __forceinline__ void operator()(int i, int j) { cx_pair(r[i], r[j], v[i], v[j]); }
 };
 
-// Sort N keys held in registers with the network of family F.
+// "Family" 2 is not a network: the textbook insertion sort the paper measures
+// the networks against ("IS Def", Section 4.2), as the baseline variant.
+constexpr int kFamilyInsertion = 2;
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// Insertion sort of N keys (and values) held in registers: key i is moved left
+// past every larger key (strict compare, so it is stable), as in the textbook
+// loop.  Channel indices are compile-time constants (fully unrolled, no
+// dynamic register indexing); the inner loop ends as soon as no lane of the
+// wave is still shifting, so an already sorted input costs one compare per
+// key, as on the CPU, and the cost of a wave is that of its slowest lane.
+template <int N, class K, bool V>
+__device__ __forceinline__ void insertion_sort_regs(K (&r)[N], uint32_t* v) {
+#pragma unroll
+  for (int i = 1; i < N; ++i) {
+    const K x = r[i];
+    uint32_t xv = 0;
+    if constexpr (V) xv = v[i];
+    bool go = true;  // this lane has not placed x yet
+#pragma unroll
+    for (int j = i - 1; j >= 0; --j) {
+      if (!wave_any(go)) break;
+      const bool shift = go && r[j] > x;
+      // shifting: r[j] moves up; stopping here: x lands at j + 1
+      r[j + 1] = shift ? r[j] : (go ? x : r[j + 1]);
+      if constexpr (V) v[j + 1] = shift ? v[j] : (go ? xv : v[j + 1]);
+      go = shift;
+    }
+    if (go) {
+      r[0] = x;
+      if constexpr (V) v[0] = xv;
+    }
+  }
+}
+
+// Textbook insertion sort of one array of n keys (and values) in place in
+// global memory, by one lane: the larger-sets half of the paper's IS+SN
+// hybrid (Section 4.6: networks up to 16 keys, insertion sort above).  Keys
+// are compared after XOR with flip (the sign-bit map of signed keys).
+template <class K, bool V>
+__device__ __forceinline__ void insertion_sort_global(K* p, uint32_t* pv, int n, K flip) {
+  for (int i = 1; i < n; ++i) {
+    const K xs = p[i];
+    const K x = xs ^ flip;
+    uint32_t xv = 0;
+    if constexpr (V) xv = pv[i];
+    int j = i - 1;
+    while (j >= 0) {
+      const K ys = p[j];
+      if (!((ys ^ flip) > x)) break;
+      p[j + 1] = ys;
+      if constexpr (V) pv[j + 1] = pv[j];
+      --j;
+    }
+    p[j + 1] = xs;
+    if constexpr (V) pv[j + 1] = xv;
+  }
+}
+
+// Sort N keys held in registers with the network of family F (or, for
+// kFamilyInsertion, with insertion sort).
 template <int F, int N, class K>
 __device__ __forceinline__ void net_sort(K (&r)[N]) {
-  KeyOp<K, N> op{r};
-  Net<F, N>::run(op);
+  if constexpr (F == kFamilyInsertion) {
+    insertion_sort_regs<N, K, false>(r, nullptr);
+  } else {
+    KeyOp<K, N> op{r};
+    Net<F, N>::run(op);
+  }
 }
 template <int F, int N, class K>
 __device__ __forceinline__ void net_sort(K (&r)[N], uint32_t (&v)[N]) {
-  PairOp<K, N> op{r, v};
-  Net<F, N>::run(op);
+  if constexpr (F == kFamilyInsertion) {
+    insertion_sort_regs<N, K, true>(r, v);
+  } else {
+    PairOp<K, N> op{r, v};
+    Net<F, N>::run(op);
+  }
 }
 
 // --- wave helpers ---------------------------------------------------------

@@ -271,13 +271,19 @@ hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStre
 
 hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
                             hipStream_t s) {
-  return tuning().family == 1 ? launch_fixed_f<1>(keys, n, count, stride, flip, s)
-                              : launch_fixed_f<0>(keys, n, count, stride, flip, s);
+  switch (tuning().family) {
+    case 1: return launch_fixed_f<1>(keys, n, count, stride, flip, s);
+    case kFamilyInsertion: return launch_fixed_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
+    default: return launch_fixed_f<0>(keys, n, count, stride, flip, s);
+  }
 }
 hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
                             hipStream_t s) {
-  return tuning().family == 1 ? launch_fixed_f<1>(keys, n, count, stride, flip, s)
-                              : launch_fixed_f<0>(keys, n, count, stride, flip, s);
+  switch (tuning().family) {
+    case 1: return launch_fixed_f<1>(keys, n, count, stride, flip, s);
+    case kFamilyInsertion: return launch_fixed_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
+    default: return launch_fixed_f<0>(keys, n, count, stride, flip, s);
+  }
 }
 
 }  // namespace ss

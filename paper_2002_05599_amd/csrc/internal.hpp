@@ -8,7 +8,7 @@ namespace ss {
 
 // Variant choices, set by the autotuner through ss_set_tuning_value.
 struct Tuning {
-  int family = 0;        // network family for n <= 16 (0 fewest comparators, 1 Bose-Nelson)
+  int family = 0;        // n <= 16: 0 fewest-comparator networks, 1 Bose-Nelson, 2 insertion sort
   int rss_k[3] = {16, 32, 64};  // level-0 bucket count for 17..64, 65..128, 129..256 keys
   int persist_occ = 0;   // work-groups per CU for the persistent grid (0 = occupancy limit)
   int rss_rounds = 16;    // rounds of groups per RSS tile in the segmented kernels
@@ -16,6 +16,7 @@ struct Tuning {
   int persist_split = 1;  // 1: one persistent kernel per kind (networks, each RSS class); 0: one for all
   int net_mix = 0;        // 1: persistent forms sort 2..16-key segments in batch order, mixed sizes
   int rss_level_cap = 8;  // RSS levels before the rank-counting fallback finishes a pending bucket
+  int large_sort = 0;     // 17..256 keys: 0 Register Sample Sort, 1 insertion sort (the IS+SN hybrid)
 };
 Tuning tuning();  // a consistent copy of the current settings
 

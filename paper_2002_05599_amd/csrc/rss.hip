@@ -23,6 +23,24 @@ rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K f
   rss_group_sort<F, K, false, G>(lds[wave * kGroups + g], gk, nullptr, m, flip, k0, level_cap);
 }
 
+// The IS+SN alternative for 17..256 keys: one lane per array, insertion sort
+// in global memory.
+template <class K>
+__global__ void __launch_bounds__(kRssThreads)
+is_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip) {
+  const int64_t arr = (int64_t)blockIdx.x * kRssThreads + threadIdx.x;
+  if (arr < count) insertion_sort_global<K, false>(keys + arr * stride, nullptr, n, flip);
+}
+
+template <class K>
+static hipError_t launch_is_fixed(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+  const int64_t blocks = (count + kRssThreads - 1) / kRssThreads;
+  if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(is_fixed_kernel<K>, dim3((unsigned)blocks), dim3(kRssThreads), 0, s, keys, n, count, stride,
+                     flip);
+  return hipGetLastError();
+}
+
 template <int F, class K, int G>
 static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, K flip, int k0,
                                int level_cap, hipStream_t s) {
@@ -46,15 +64,23 @@ hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t st
                                 int* status, hipStream_t s) {
   (void)status;
   if (n < 17 || n > kMaxN) return hipErrorInvalidValue;
-  return tuning().family == 1 ? launch_rss_f<1>(keys, n, count, stride, flip, s)
-                              : launch_rss_f<0>(keys, n, count, stride, flip, s);
+  if (tuning().large_sort == 1) return launch_is_fixed(keys, n, count, stride, flip, s);
+  switch (tuning().family) {
+    case 1: return launch_rss_f<1>(keys, n, count, stride, flip, s);
+    case kFamilyInsertion: return launch_rss_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
+    default: return launch_rss_f<0>(keys, n, count, stride, flip, s);
+  }
 }
 hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
                                 int* status, hipStream_t s) {
   (void)status;
   if (n < 17 || n > kMaxN) return hipErrorInvalidValue;
-  return tuning().family == 1 ? launch_rss_f<1>(keys, n, count, stride, flip, s)
-                              : launch_rss_f<0>(keys, n, count, stride, flip, s);
+  if (tuning().large_sort == 1) return launch_is_fixed(keys, n, count, stride, flip, s);
+  switch (tuning().family) {
+    case 1: return launch_rss_f<1>(keys, n, count, stride, flip, s);
+    case kFamilyInsertion: return launch_rss_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
+    default: return launch_rss_f<0>(keys, n, count, stride, flip, s);
+  }
 }
 
 }  // namespace ss

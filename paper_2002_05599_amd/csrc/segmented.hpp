@@ -305,6 +305,22 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
   }
 }
 
+// The IS+SN alternative for the RSS classes: the tile's segments sorted one
+// per lane by insertion sort in global memory (64 segments per pass).
+template <class K, bool V>
+__device__ __forceinline__ void is_tile(K* keys, uint32_t* vals, const int32_t* __restrict__ offsets,
+                                        const int32_t* __restrict__ ids, int list, int count, int first, int ntile,
+                                        K flip) {
+  for (int j0 = 0; j0 < ntile; j0 += kWave) {
+    const int j = first + j0 + lane_id();
+    if (j0 + lane_id() < ntile && j < count) {
+      const int seg = ids[list + j];
+      const int lo = offsets[seg];
+      insertion_sort_global<K, V>(keys + lo, V ? vals + lo : nullptr, offsets[seg + 1] - lo, flip);
+    }
+  }
+}
+
 struct SortArgs {
   const int32_t* offsets;
   const int32_t* ids;
@@ -315,6 +331,7 @@ struct SortArgs {
   int interleave;  // alternate RSS and network tiles in the persistent kernel
   int net_mix;     // class 0 holds every network size, in batch order
   int level_cap;   // RSS levels before the rank-counting fallback
+  int large_sort;  // 1: the RSS classes are sorted by insertion sort (IS+SN)
 };
 
 // Kind sets of the persistent kernels: every class (one kernel holding every
@@ -345,6 +362,12 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint3
         net_tile_mixed<F, K, V>(keys, vals, a.offsets, a.ids, list, count, first, flip);
       else
         net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
+      return;
+    }
+  }
+  if constexpr (KS == kKindAll || !is_net_kind(KS)) {
+    if (a.large_sort && c >= kNetClasses) {
+      is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, first, class_tile(c, rounds), flip);
       return;
     }
   }
@@ -468,8 +491,11 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
     const int list = (int)a.ctrl[kCtrlStart + kClass];
     const int k0 = a.k0[KS - kKindRss16];
     auto run_units = [&](int u, int n) {
-      rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0,
-                           a.level_cap);
+      if (a.large_sort)
+        is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, u * kGroups, n * kGroups, flip);
+      else
+        rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0,
+                             a.level_cap);
     };
     const int units = (count + kGroups - 1) / kGroups;
     const int R = class_rounds(kClass, count, a.rounds, waves, kPersistTpw);
@@ -570,6 +596,8 @@ seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, 
   const int first = tile * class_tile(c, rounds);
   if constexpr (KIND == 0) {
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
+  } else if (a.large_sort) {
+    is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, first, class_tile(c, rounds), flip);
   } else if constexpr (KIND == 1) {
     rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
                           a.k0[0], a.level_cap);
@@ -646,6 +674,7 @@ inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
   a.interleave = t.interleave;
   a.net_mix = t.net_mix;
   a.level_cap = t.rss_level_cap;
+  a.large_sort = t.large_sort;
   return a;
 }
 
@@ -814,7 +843,7 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
 
 template <int F, class K, bool V>
 static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
-  const int key = (((int)sizeof(K) * 4 + (V ? 2 : 0) + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0);
+  const int key = ((((int)sizeof(K) * 2 + (V ? 1 : 0)) * 3 + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0);
   GraphEntry* g = nullptr;
   for (GraphEntry& ge : sc->graphs)
     if (ge.key == key && std::equal(ge.persist_blocks, ge.persist_blocks + kKinds, L.persist_blocks)) g = &ge;
@@ -862,8 +891,8 @@ static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
 }
 
 template <int F, class K, bool V>
-static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets,
-                          int32_t nseg, K flip, int mode, hipStream_t s) {
+int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
+                   K flip, int mode, hipStream_t s) {
   SegLaunch<F, K, V> L;
   init_launch(c, L);
   L.fill(c, ws->buffers(), keys, vals, offsets, nseg, flip);
@@ -878,6 +907,36 @@ static int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* v
   return e == hipSuccess ? 0 : -4;
 }
 
+// The no-allocation form: binning and persistent kernels launched directly on
+// caller-provided buffers (the fixed scratch array); no graph, no allocation.
+template <int F, class K, bool V>
+int segmented_direct_impl(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals, const int32_t* offsets,
+                          int32_t nseg, K flip, hipStream_t s) {
+  SegLaunch<F, K, V> L;
+  init_launch(c, L);
+  L.fill(c, b, keys, vals, offsets, nseg, flip);
+  return L.launch_direct(s) == hipSuccess ? 0 : -4;
+}
+
+// Every (family, key width, payload) combination of the segmented path.  Each
+// is compiled in an instantiation unit of its own (written by the build into
+// _build/, one explicit instantiation per unit, so the units compile in
+// parallel); every other unit only refers to them.
+#define SS_SEGMENTED_COMBOS(X)                                                                   \
+  X(0, uint32_t, false) X(0, uint32_t, true) X(1, uint32_t, false) X(1, uint32_t, true)          \
+  X(2, uint32_t, false) X(2, uint32_t, true) X(0, uint64_t, false) X(0, uint64_t, true)          \
+  X(1, uint64_t, false) X(1, uint64_t, true) X(2, uint64_t, false) X(2, uint64_t, true)
+
+#define SS_SEGMENTED_DECLARE(F, K, V, EXT)                                                              \
+  EXT template int segmented_impl<F, K, V>(DeviceCtx*, SegmentedCache*, K*, uint32_t*, const int32_t*, \
+                                           int32_t, K, int, hipStream_t);                               \
+  EXT template int segmented_direct_impl<F, K, V>(DeviceCtx*, const SegBuffers&, K*, uint32_t*,        \
+                                                  const int32_t*, int32_t, K, hipStream_t);
+#define SS_SEGMENTED_EXTERN(F, K, V) SS_SEGMENTED_DECLARE(F, K, V, extern)
+#ifndef SS_SEGMENTED_INSTANCE_UNIT
+SS_SEGMENTED_COMBOS(SS_SEGMENTED_EXTERN)
+#endif
+
 template <class K>
 static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, K flip,
                          int mode, hipStream_t s) {
@@ -886,34 +945,33 @@ static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* o
   std::lock_guard<std::mutex> lock(ws->mu);
   hipError_t e = ensure_workspace(ws, nseg, s);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? -5 : -4;
-  const bool fam = tuning().family == 1;
-  if (vals)
-    return fam ? segmented_impl<1, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
-               : segmented_impl<0, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
-  return fam ? segmented_impl<1, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
-             : segmented_impl<0, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
-}
-
-// The no-allocation form: binning and persistent kernels launched directly on
-// caller-provided buffers (the fixed scratch array); no graph, no allocation.
-template <int F, class K, bool V>
-static int segmented_direct_impl(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals,
-                                 const int32_t* offsets, int32_t nseg, K flip, hipStream_t s) {
-  SegLaunch<F, K, V> L;
-  init_launch(c, L);
-  L.fill(c, b, keys, vals, offsets, nseg, flip);
-  return L.launch_direct(s) == hipSuccess ? 0 : -4;
+  switch (tuning().family) {
+    case 1:
+      return vals ? segmented_impl<1, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
+                  : segmented_impl<1, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
+    case kFamilyInsertion:
+      return vals ? segmented_impl<kFamilyInsertion, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
+                  : segmented_impl<kFamilyInsertion, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
+    default:
+      return vals ? segmented_impl<0, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
+                  : segmented_impl<0, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
+  }
 }
 
 template <class K>
 static int segmented_direct_any(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals,
                                 const int32_t* offsets, int32_t nseg, K flip, hipStream_t s) {
-  const bool fam = tuning().family == 1;
-  if (vals)
-    return fam ? segmented_direct_impl<1, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
-               : segmented_direct_impl<0, K, true>(c, b, keys, vals, offsets, nseg, flip, s);
-  return fam ? segmented_direct_impl<1, K, false>(c, b, keys, vals, offsets, nseg, flip, s)
-             : segmented_direct_impl<0, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
+  switch (tuning().family) {
+    case 1:
+      return vals ? segmented_direct_impl<1, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
+                  : segmented_direct_impl<1, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
+    case kFamilyInsertion:
+      return vals ? segmented_direct_impl<kFamilyInsertion, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
+                  : segmented_direct_impl<kFamilyInsertion, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
+    default:
+      return vals ? segmented_direct_impl<0, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
+                  : segmented_direct_impl<0, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
+  }
 }
 
 }  // namespace ss

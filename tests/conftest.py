@@ -9,7 +9,7 @@ if ROOT not in sys.path:
 
 # every tuning knob the library exposes (include/smallsort.h)
 TUNING_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "persist_occ", "rss_rounds",
-                "interleave", "persist_split", "net_mix", "rss_level_cap", "large_base")
+                "interleave", "persist_split", "net_mix", "rss_level_cap", "large_sort")
 
 
 def pytest_configure(config):

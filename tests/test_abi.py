@@ -101,6 +101,9 @@ def test_tuning_roundtrip(lib, tmp_path):
     f.write_text('{"rss_k_small": 4, ')
     with pytest.raises(ss.SmallSortError):
         ss.load_tuning(str(f))
+    for name, bad in (("family", 3), ("large_sort", 2)):
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning(name, bad)
     ss.set_tuning("family", old_family)
     ss.set_tuning("rss_k_small", old)
     old_cap = ss.get_tuning("rss_level_cap")
@@ -123,3 +126,11 @@ def test_binding_maps_one_hip_runtime():
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_library_leaves_no_symbol_of_its_own_undefined():
+    """Every kernel set the dispatch refers to was instantiated in some unit."""
+    import subprocess
+    r = subprocess.run(["nm", "-uC", ss.lib_path()], capture_output=True, text=True, check=True)
+    missing = [ln for ln in r.stdout.splitlines() if "ss::" in ln]
+    assert not missing, missing

@@ -30,7 +30,7 @@ def run_fixed(keys_np, n, count, stride):
     return from_dev(t)
 
 
-FAMILIES = [0, 1]
+FAMILIES = [0, 1, 2]  # fewest comparators, Bose-Nelson, insertion sort
 
 
 @pytest.mark.parametrize("family", FAMILIES, ids=lambda f: f"family{f}")

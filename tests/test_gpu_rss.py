@@ -87,13 +87,15 @@ def test_rss_every_size_u32():
 TUNINGS = [("rss_k_small", 4), ("rss_k_small", 8), ("rss_k_small", 16),
            ("rss_k_mid", 4), ("rss_k_mid", 8), ("rss_k_mid", 16), ("rss_k_mid", 32),
            ("rss_k_large", 4), ("rss_k_large", 8), ("rss_k_large", 16), ("rss_k_large", 32),
-           ("rss_k_large", 64), ("family", 0), ("family", 1)]
+           ("rss_k_large", 64), ("family", 0), ("family", 1), ("family", 2), ("large_sort", 1)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t[0]}={t[1]}")
 def test_rss_tuning_variants(tuning):
-    """Every first-level bucket count and family: uniform keys of every class,
-    duplicate-heavy keys (three-way splits) and 64-bit keys."""
+    """Every first-level bucket count and family (2: buckets finished by
+    insertion sort), and insertion sort in place of RSS (large_sort=1, the
+    IS+SN hybrid): uniform keys of every class, duplicate-heavy keys
+    (three-way splits) and 64-bit keys."""
     name, value = tuning
     old = ss.get_tuning(name)
     ss.set_tuning(name, value)

@@ -308,10 +308,11 @@ def test_persistent_kernel_forms(form, mode):
         assert ss.device_status() == 0
 
 
-@pytest.mark.parametrize("family", [0, 1])
+@pytest.mark.parametrize("family", [0, 1, 2])
 @pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
 def test_network_families_segmented(family, mode):
-    """Both network families in the segmented network tiles and RSS finishing."""
+    """Both network families and insertion sort (family 2) in the segmented
+    network tiles and RSS finishing."""
     from helpers import tuned
     with tuned(family=family):
         sizes = inputs.geometric_sizes(20000, seed=21)
@@ -363,3 +364,27 @@ def test_stream_copy_probe():
     assert torch.equal(dst, src)
     with pytest.raises(ss.SmallSortError):
         ss.stream_copy(dst[1:], src[1:])
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_insertion_sort_above_16_segmented(mode):
+    """The IS+SN hybrid (large_sort=1): segments of 17..256 keys sorted by
+    insertion sort, 2..16 by networks; mixed sizes, payload, duplicates."""
+    from helpers import tuned
+    rng = np.random.default_rng(41)
+    sizes = np.concatenate([rng.integers(0, 257, size=3000), rng.integers(0, 17, size=2000)])
+    rng.shuffle(sizes)
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    with tuned(large_sort=1):
+        keys = inputs.distinct_u64(total, seed=42)
+        vals = inputs.segment_index_payload(off)
+        gk, gv = run_seg(keys, off, vals, mode=mode)
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (gk == wk).all() and (gv == wv).all()
+        k32 = inputs.random_keys(np.int32, total, seed=43)
+        k32[rng.random(total) < 0.3] = -5
+        got, _ = run_seg(k32, off, mode=mode)
+        want, _ = oracle.sort_segments(k32, off)
+        assert (got == want).all(), first_mismatch(got, want)
+        assert ss.device_status() == 0
