@@ -18,7 +18,12 @@
  *     ss_segmented_sort, which say so.
  *   - Sorting is in place and ascending (non-decreasing): the lower channel of
  *     every comparator receives the smaller key (Section 2.1).
- *   - Signed keys are ordered as two's-complement integers.
+ *   - Signed keys are ordered as two's-complement integers.  Float and double
+ *     keys are ordered by IEEE 754 totalOrder: -NaN < -inf < ... < -0 < +0 <
+ *     ... < +inf < +NaN (NaNs of one sign by their payload bits).  Without NaNs
+ *     this is non-decreasing order under the float comparison, with -0 placed
+ *     before +0 (the paper compares floats with the CPU's compare instruction,
+ *     Section 2.2; a total order keeps every result unique).
  *   - With a payload (`vals` != NULL, a uint32 array parallel to the keys) the
  *     (key, value) pairs are permuted together.  Equal keys may come out in
  *     any order relative to each other (networks are not stable), so the
@@ -68,6 +73,8 @@ typedef int32_t ss_status;
 #define SS_KEY_I32 1
 #define SS_KEY_U64 2
 #define SS_KEY_I64 3
+#define SS_KEY_F32 4
+#define SS_KEY_F64 5
 
 /* Execution modes for ss_segmented_sort. */
 #define SS_MODE_AUTO       0  /* persistent kernel, replayed from a cached hipGraph */
@@ -90,6 +97,8 @@ ss_status sort_small_u32(uint32_t *keys, int32_t n, int64_t count, int64_t strid
 ss_status sort_small_i32(int32_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
 ss_status sort_small_u64(uint64_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
 ss_status sort_small_i64(int64_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
+ss_status sort_small_f32(float *keys, int32_t n, int64_t count, int64_t stride, void *stream);
+ss_status sort_small_f64(double *keys, int32_t n, int64_t count, int64_t stride, void *stream);
 
 /*
  * Segmented layout (CSR): segment i is [offsets[i], offsets[i+1]) for
@@ -108,6 +117,8 @@ ss_status segmented_sort_u32(uint32_t *keys, uint32_t *vals, const int32_t *offs
 ss_status segmented_sort_i32(int32_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
 ss_status segmented_sort_u64(uint64_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
 ss_status segmented_sort_i64(int64_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
+ss_status segmented_sort_f32(float *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
+ss_status segmented_sort_f64(double *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);
 
 /*
  * Generic segmented entry point: key_type is an SS_KEY_* code, mode an
@@ -119,6 +130,21 @@ ss_status segmented_sort_i64(int64_t *keys, uint32_t *vals, const int32_t *offse
  */
 ss_status ss_segmented_sort(int32_t key_type, void *keys, uint32_t *vals, const int32_t *offsets,
                             int32_t nseg, int32_t mode, void *stream);
+
+/*
+ * Segmented sort with a payload of either width: vals is NULL (keys only) or a
+ * device array parallel to keys of val_bytes = 4 (uint32) or 8 (uint64; 64-bit
+ * key types only) per key.  With 64-bit keys and 8-byte values this sorts the
+ * paper's items, a 64-bit key with a 64-bit reference (Section 2.2), stored as
+ * two parallel arrays.  Errors as ss_segmented_sort; SS_EINVAL for another
+ * val_bytes or for 8-byte values with 32-bit keys; SS_EALIGN if vals is not
+ * aligned to val_bytes.
+ */
+ss_status ss_segmented_sort_v(int32_t key_type, void *keys, void *vals, int32_t val_bytes, const int32_t *offsets,
+                              int32_t nseg, int32_t mode, void *stream);
+/* ss_segmented_sort_v(SS_KEY_U64, keys, refs, 8, offsets, nseg, SS_MODE_AUTO, stream). */
+ss_status segmented_sort_pairs_u64(uint64_t *keys, uint64_t *refs, const int32_t *offsets, int32_t nseg,
+                                   void *stream);
 
 /*
  * No-allocation form of ss_segmented_sort, for callers that cannot allocate

@@ -23,7 +23,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 _SUFFIX = {np.dtype(np.uint32): "u32", np.dtype(np.int32): "i32",
-           np.dtype(np.uint64): "u64", np.dtype(np.int64): "i64"}
+           np.dtype(np.uint64): "u64", np.dtype(np.int64): "i64",
+           np.dtype(np.float32): "f32", np.dtype(np.float64): "f64"}
+# key types that also take a 64-bit payload (names ending in _v64)
+_V64 = ("u64", "i64", "f64")
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -34,7 +37,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         _build.build(out=path)
     lib = ctypes.CDLL(path)
-    for s in _SUFFIX.values():
+    for s in list(_SUFFIX.values()) + [f"{k}_v64" for k in _V64]:
         getattr(lib, f"oracle_insertion_sort_{s}").argtypes = [_P, _P, _I64]
         getattr(lib, f"oracle_insertion_sort_{s}").restype = None
         for name in ("merge_sort", "sort"):
@@ -62,11 +65,24 @@ def _get(lib=None):
     return _lib
 
 
-def _suffix(keys: np.ndarray) -> str:
+def _suffix(keys: np.ndarray, vals=None) -> str:
     try:
-        return _SUFFIX[keys.dtype]
+        s = _SUFFIX[keys.dtype]
     except KeyError:
         raise TypeError(f"unsupported key dtype {keys.dtype}") from None
+    if vals is not None and vals.dtype == np.uint64:
+        if s not in _V64:
+            raise TypeError("a 64-bit payload needs 64-bit keys")
+        s += "_v64"
+    return s
+
+
+def _vals_copy(vals):
+    """A copy of the payload as uint64 if it is uint64, else as uint32."""
+    if vals is None:
+        return None
+    v = np.asarray(vals)
+    return np.array(v, dtype=np.uint64 if v.dtype == np.uint64 else np.uint32, copy=True)
 
 
 def _ptr(a):
@@ -81,24 +97,24 @@ def _check(rc):
 def insertion_sort(keys, vals=None, lib=None):
     """Insertion sort of one 1-D array (any n); returns (keys, vals) copies."""
     k = np.array(keys, copy=True)
-    v = None if vals is None else np.array(vals, dtype=np.uint32, copy=True)
-    getattr(_get(lib), f"oracle_insertion_sort_{_suffix(k)}")(_ptr(k), _ptr(v), k.size)
+    v = _vals_copy(vals)
+    getattr(_get(lib), f"oracle_insertion_sort_{_suffix(k, v)}")(_ptr(k), _ptr(v), k.size)
     return k, v
 
 
 def merge_sort(keys, vals=None, lib=None):
     """Top-down merge sort of one 1-D array (any n); returns copies."""
     k = np.array(keys, copy=True)
-    v = None if vals is None else np.array(vals, dtype=np.uint32, copy=True)
-    _check(getattr(_get(lib), f"oracle_merge_sort_{_suffix(k)}")(_ptr(k), _ptr(v), k.size))
+    v = _vals_copy(vals)
+    _check(getattr(_get(lib), f"oracle_merge_sort_{_suffix(k, v)}")(_ptr(k), _ptr(v), k.size))
     return k, v
 
 
 def sort_one(keys, vals=None, lib=None):
     """The dispatching sort: insertion sort if n <= 16, else merge sort."""
     k = np.array(keys, copy=True)
-    v = None if vals is None else np.array(vals, dtype=np.uint32, copy=True)
-    _check(getattr(_get(lib), f"oracle_sort_{_suffix(k)}")(_ptr(k), _ptr(v), k.size))
+    v = _vals_copy(vals)
+    _check(getattr(_get(lib), f"oracle_sort_{_suffix(k, v)}")(_ptr(k), _ptr(v), k.size))
     return k, v
 
 
@@ -153,10 +169,10 @@ def sort_fixed_inplace(k, n, count, stride, lib=None, threads=1):
 def sort_segments(keys, offsets, vals=None, lib=None, threads=1):
     """Sort CSR segments [offsets[i], offsets[i+1]); returns (keys, vals) copies."""
     k = np.array(keys, copy=True)
-    v = None if vals is None else np.array(vals, dtype=np.uint32, copy=True)
+    v = _vals_copy(vals)
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     nseg = off.size - 1
-    f = getattr(_get(lib), f"oracle_sort_segments_{_suffix(k)}")
+    f = getattr(_get(lib), f"oracle_sort_segments_{_suffix(k, v)}")
     if threads <= 1 or nseg < 2 * threads:
         _check(f(_ptr(k), _ptr(v), _ptr(off), max(nseg, 0)))
         return k, v

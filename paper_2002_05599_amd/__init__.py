@@ -25,8 +25,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_NAME = "libsmallsort.so"
 
 MODE_AUTO, MODE_PERSISTENT, MODE_PLAIN = 0, 1, 2
-KEY_CODES = {"uint32": 0, "int32": 1, "uint64": 2, "int64": 3}
-_SUFFIX = {"uint32": "u32", "int32": "i32", "uint64": "u64", "int64": "i64"}
+KEY_CODES = {"uint32": 0, "int32": 1, "uint64": 2, "int64": 3, "float32": 4, "float64": 5}
+_SUFFIX = {"uint32": "u32", "int32": "i32", "uint64": "u64", "int64": "i64", "float32": "f32", "float64": "f64"}
 
 # Every symbol include/smallsort.h declares, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -44,6 +44,9 @@ _SIGS = {
     "ss_version": (ctypes.c_char_p, []),
     "ss_stream_copy": (ctypes.c_int32, [_P, _P, ctypes.c_int64, _P]),
     "ss_segmented_sort_noalloc": (ctypes.c_int32, [ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P]),
+    "ss_segmented_sort_v": (ctypes.c_int32, [ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
+                                             ctypes.c_int32, _P]),
+    "segmented_sort_pairs_u64": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P]),
 }
 
 NOALLOC_MAX_SEGMENTS = 1 << 24  # SS_NOALLOC_MAX_SEGMENTS
@@ -136,7 +139,7 @@ def _check(status, what):
 def _dtype_name(t):
     name = str(t.dtype).replace("torch.", "")
     if name not in _SUFFIX:
-        raise TypeError(f"unsupported key dtype {t.dtype}; use uint32, int32, uint64 or int64")
+        raise TypeError(f"unsupported key dtype {t.dtype}; use uint32, int32, uint64, int64, float32 or float64")
     return name
 
 
@@ -177,7 +180,8 @@ def segmented_sort(keys, offsets, vals=None, mode=MODE_AUTO, stream=None):
     """Sort CSR segments ``[offsets[i], offsets[i+1])`` of ``keys`` in place.
 
     ``offsets``: device int32 tensor of nseg+1 entries.  ``vals``: optional
-    device uint32 tensor permuted with the keys.  ``mode``: MODE_AUTO
+    device uint32 tensor (or uint64, with 64-bit keys: the key + reference
+    items of Section 2.2) permuted with the keys.  ``mode``: MODE_AUTO
     (persistent kernel from a cached graph), MODE_PERSISTENT (no graph) or
     MODE_PLAIN (one launch per size class).
     """
@@ -187,16 +191,17 @@ def segmented_sort(keys, offsets, vals=None, mode=MODE_AUTO, stream=None):
     if str(offsets.dtype) != "torch.int32":
         raise TypeError("offsets must be int32")
     nseg = offsets.numel() - 1
-    vptr = None
+    vptr, vbytes = None, 4
     if vals is not None:
         _require_cuda(vals, "vals")
-        if str(vals.dtype) != "torch.uint32" or vals.numel() != keys.numel():
-            raise TypeError("vals must be a uint32 tensor shaped like keys")
+        if str(vals.dtype) not in ("torch.uint32", "torch.uint64") or vals.numel() != keys.numel():
+            raise TypeError("vals must be a uint32 or uint64 tensor shaped like keys")
         vptr = ctypes.c_void_p(vals.data_ptr())
-    st = lib().ss_segmented_sort(KEY_CODES[name], ctypes.c_void_p(keys.data_ptr()), vptr,
-                                 ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), int(mode),
-                                 _stream_ptr(stream))
-    _check(st, "ss_segmented_sort")
+        vbytes = vals.element_size()
+    st = lib().ss_segmented_sort_v(KEY_CODES[name], ctypes.c_void_p(keys.data_ptr()), vptr, vbytes,
+                                   ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), int(mode),
+                                   _stream_ptr(stream))
+    _check(st, "ss_segmented_sort_v")
     return keys, vals
 
 

@@ -73,55 +73,67 @@ static ss_status check_fixed(const void* keys, int32_t n, int64_t count, int64_t
   return SS_OK;
 }
 
-template <class K>
-static ss_status sort_small(K* keys, int32_t n, int64_t count, int64_t stride, K flip, hipStream_t s) {
-  ss_status st = check_fixed<K>(keys, n, count, stride);
+// W: the unsigned word of the key's width; map: the key type's order-preserving map.
+template <class W>
+static ss_status sort_small(void* keys_v, int32_t n, int64_t count, int64_t stride, KeyMap<W> map, hipStream_t s) {
+  W* keys = static_cast<W*>(keys_v);
+  ss_status st = check_fixed<W>(keys, n, count, stride);
   if (st == 1) return SS_OK;
   if (st != SS_OK) return st;
   hipError_t herr = hipSuccess;
   if (n <= SS_MAX_NETWORK_N) {
-    if constexpr (sizeof(K) == 4)
-      herr = launch_fixed_u32(reinterpret_cast<uint32_t*>(keys), n, count, stride, (uint32_t)flip, s);
+    if constexpr (sizeof(W) == 4)
+      herr = launch_fixed_u32(keys, n, count, stride, map, s);
     else
-      herr = launch_fixed_u64(reinterpret_cast<uint64_t*>(keys), n, count, stride, (uint64_t)flip, s);
+      herr = launch_fixed_u64(keys, n, count, stride, map, s);
     return from_hip(herr);
   }
   DeviceCtx* c = device_ctx(&herr);
   if (!c) return from_hip(herr);
-  if constexpr (sizeof(K) == 4)
-    herr = launch_rss_fixed_u32(reinterpret_cast<uint32_t*>(keys), n, count, stride, (uint32_t)flip,
-                                c->status, s);
+  if constexpr (sizeof(W) == 4)
+    herr = launch_rss_fixed_u32(keys, n, count, stride, map, c->status, s);
   else
-    herr = launch_rss_fixed_u64(reinterpret_cast<uint64_t*>(keys), n, count, stride, (uint64_t)flip,
-                                c->status, s);
+    herr = launch_rss_fixed_u64(keys, n, count, stride, map, c->status, s);
   return from_hip(herr);
 }
 
-static ss_status segmented(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
+static bool key_is_64(int32_t key_type) {
+  return key_type == SS_KEY_U64 || key_type == SS_KEY_I64 || key_type == SS_KEY_F64;
+}
+
+template <class W>
+static KeyMap<W> key_map(int32_t key_type) {
+  switch (key_type) {
+    case SS_KEY_I32:
+    case SS_KEY_I64: return kSignedMap<W>;
+    case SS_KEY_F32:
+    case SS_KEY_F64: return kFloatMap<W>;
+    default: return kUnsignedMap<W>;
+  }
+}
+
+// vbytes: payload bytes per key (0 when vals is NULL, 4, or 8 with 64-bit keys).
+static ss_status segmented(int32_t key_type, void* keys, void* vals, int32_t vbytes, const int32_t* offsets,
                            int32_t nseg, int32_t mode, hipStream_t s) {
-  if (key_type < SS_KEY_U32 || key_type > SS_KEY_I64) return SS_EINVAL;
+  if (key_type < SS_KEY_U32 || key_type > SS_KEY_F64) return SS_EINVAL;
   if (mode < SS_MODE_AUTO || mode > SS_MODE_PLAIN) return SS_EINVAL;
+  if (vbytes != 4 && vbytes != 8) return SS_EINVAL;
+  if (vbytes == 8 && !key_is_64(key_type)) return SS_EINVAL;
   if (nseg < 0) return SS_EINVAL;
   if (nseg == 0) return SS_OK;
   if (keys == nullptr || offsets == nullptr) return SS_EINVAL;
-  const size_t ksz = (key_type == SS_KEY_U32 || key_type == SS_KEY_I32) ? 4 : 8;
+  const size_t ksz = key_is_64(key_type) ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(keys) % ksz != 0) return SS_EALIGN;
   if (reinterpret_cast<uintptr_t>(offsets) % 4 != 0) return SS_EALIGN;
-  if (vals && reinterpret_cast<uintptr_t>(vals) % 4 != 0) return SS_EALIGN;
+  if (vals && reinterpret_cast<uintptr_t>(vals) % vbytes != 0) return SS_EALIGN;
+  const int vb = vals ? vbytes : 0;
   hipError_t herr = hipSuccess;
   DeviceCtx* c = device_ctx(&herr);
   if (!c) return from_hip(herr);
-  switch (key_type) {
-    case SS_KEY_U32:
-      return segmented_u32(c, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0u, mode, s);
-    case SS_KEY_I32:
-      return segmented_u32(c, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0x80000000u, mode, s);
-    case SS_KEY_U64:
-      return segmented_u64(c, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0ull, mode, s);
-    default:
-      return segmented_u64(c, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0x8000000000000000ull,
-                           mode, s);
-  }
+  if (key_is_64(key_type))
+    return segmented_u64(c, static_cast<uint64_t*>(keys), vals, vb, offsets, nseg, key_map<uint64_t>(key_type), mode,
+                         s);
+  return segmented_u32(c, static_cast<uint32_t*>(keys), vals, vb, offsets, nseg, key_map<uint32_t>(key_type), mode, s);
 }
 
 // The no-allocation form of `segmented`: same checks, then the binning and
@@ -130,12 +142,12 @@ static_assert(kNoAllocMaxSeg == SS_NOALLOC_MAX_SEGMENTS, "header and library agr
 
 static ss_status segmented_noalloc(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
                                    int32_t nseg, hipStream_t s) {
-  if (key_type < SS_KEY_U32 || key_type > SS_KEY_I64) return SS_EINVAL;
+  if (key_type < SS_KEY_U32 || key_type > SS_KEY_F64) return SS_EINVAL;
   if (nseg < 0) return SS_EINVAL;
   if (nseg > kNoAllocMaxSeg) return SS_ESCRATCH;
   if (nseg == 0) return SS_OK;
   if (keys == nullptr || offsets == nullptr) return SS_EINVAL;
-  const size_t ksz = (key_type == SS_KEY_U32 || key_type == SS_KEY_I32) ? 4 : 8;
+  const size_t ksz = key_is_64(key_type) ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(keys) % ksz != 0) return SS_EALIGN;
   if (reinterpret_cast<uintptr_t>(offsets) % 4 != 0) return SS_EALIGN;
   if (vals && reinterpret_cast<uintptr_t>(vals) % 4 != 0) return SS_EALIGN;
@@ -145,17 +157,12 @@ static ss_status segmented_noalloc(int32_t key_type, void* keys, uint32_t* vals,
   SegBuffers b;
   herr = noalloc_buffers(c, &b);
   if (herr != hipSuccess) return from_hip(herr);
-  switch (key_type) {
-    case SS_KEY_U32:
-      return segmented_direct_u32(c, b, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0u, s);
-    case SS_KEY_I32:
-      return segmented_direct_u32(c, b, static_cast<uint32_t*>(keys), vals, offsets, nseg, 0x80000000u, s);
-    case SS_KEY_U64:
-      return segmented_direct_u64(c, b, static_cast<uint64_t*>(keys), vals, offsets, nseg, 0ull, s);
-    default:
-      return segmented_direct_u64(c, b, static_cast<uint64_t*>(keys), vals, offsets, nseg,
-                                  0x8000000000000000ull, s);
-  }
+  const int vb = vals ? 4 : 0;
+  if (key_is_64(key_type))
+    return segmented_direct_u64(c, b, static_cast<uint64_t*>(keys), vals, vb, offsets, nseg,
+                                key_map<uint64_t>(key_type), s);
+  return segmented_direct_u32(c, b, static_cast<uint32_t*>(keys), vals, vb, offsets, nseg, key_map<uint32_t>(key_type),
+                              s);
 }
 
 // --- tuning ----------------------------------------------------------------
@@ -205,40 +212,61 @@ using namespace ss;
 extern "C" {
 
 ss_status sort_small_u32(uint32_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
-  return sort_small<uint32_t>(keys, n, count, stride, 0u, static_cast<hipStream_t>(stream));
+  return sort_small<uint32_t>(keys, n, count, stride, kUnsignedMap<uint32_t>, static_cast<hipStream_t>(stream));
 }
 ss_status sort_small_i32(int32_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
-  return sort_small<uint32_t>(reinterpret_cast<uint32_t*>(keys), n, count, stride, 0x80000000u,
-                              static_cast<hipStream_t>(stream));
+  return sort_small<uint32_t>(keys, n, count, stride, kSignedMap<uint32_t>, static_cast<hipStream_t>(stream));
 }
 ss_status sort_small_u64(uint64_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
-  return sort_small<uint64_t>(keys, n, count, stride, 0ull, static_cast<hipStream_t>(stream));
+  return sort_small<uint64_t>(keys, n, count, stride, kUnsignedMap<uint64_t>, static_cast<hipStream_t>(stream));
 }
 ss_status sort_small_i64(int64_t* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
-  return sort_small<uint64_t>(reinterpret_cast<uint64_t*>(keys), n, count, stride,
-                              0x8000000000000000ull, static_cast<hipStream_t>(stream));
+  return sort_small<uint64_t>(keys, n, count, stride, kSignedMap<uint64_t>, static_cast<hipStream_t>(stream));
+}
+ss_status sort_small_f32(float* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
+  return sort_small<uint32_t>(keys, n, count, stride, kFloatMap<uint32_t>, static_cast<hipStream_t>(stream));
+}
+ss_status sort_small_f64(double* keys, int32_t n, int64_t count, int64_t stride, void* stream) {
+  return sort_small<uint64_t>(keys, n, count, stride, kFloatMap<uint64_t>, static_cast<hipStream_t>(stream));
 }
 
 ss_status segmented_sort_u32(uint32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
                              void* stream) {
-  return segmented(SS_KEY_U32, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+  return segmented(SS_KEY_U32, keys, vals, 4, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
 }
 ss_status segmented_sort_i32(int32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
                              void* stream) {
-  return segmented(SS_KEY_I32, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+  return segmented(SS_KEY_I32, keys, vals, 4, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
 }
 ss_status segmented_sort_u64(uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
                              void* stream) {
-  return segmented(SS_KEY_U64, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+  return segmented(SS_KEY_U64, keys, vals, 4, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
 }
 ss_status segmented_sort_i64(int64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
                              void* stream) {
-  return segmented(SS_KEY_I64, keys, vals, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+  return segmented(SS_KEY_I64, keys, vals, 4, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+}
+
+ss_status segmented_sort_f32(float* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, void* stream) {
+  return segmented(SS_KEY_F32, keys, vals, 4, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
+}
+ss_status segmented_sort_f64(double* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, void* stream) {
+  return segmented(SS_KEY_F64, keys, vals, 4, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
 }
 
 ss_status ss_segmented_sort(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
                             int32_t nseg, int32_t mode, void* stream) {
-  return segmented(key_type, keys, vals, offsets, nseg, mode, static_cast<hipStream_t>(stream));
+  return segmented(key_type, keys, vals, 4, offsets, nseg, mode, static_cast<hipStream_t>(stream));
+}
+
+ss_status ss_segmented_sort_v(int32_t key_type, void* keys, void* vals, int32_t val_bytes, const int32_t* offsets,
+                              int32_t nseg, int32_t mode, void* stream) {
+  return segmented(key_type, keys, vals, val_bytes, offsets, nseg, mode, static_cast<hipStream_t>(stream));
+}
+
+ss_status segmented_sort_pairs_u64(uint64_t* keys, uint64_t* refs, const int32_t* offsets, int32_t nseg,
+                                   void* stream) {
+  return segmented(SS_KEY_U64, keys, refs, 8, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
 }
 
 ss_status ss_segmented_sort_noalloc(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,

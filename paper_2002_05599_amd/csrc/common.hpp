@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "keymap.hpp"
 #include "networks_gen.hpp"
 
 namespace ss {
@@ -21,6 +22,12 @@ constexpr int kStatusTooBig = -3;
 // unsigned by flipping its sign bit on load and back on store; this map is
 // order-preserving, so the unsigned network sorts signed keys in
 // two's-complement order.
+// Payload word for a payload of VB bytes per key (VB = 0: no payload; the
+// type is then a placeholder that is never read or written).
+template <int VB> struct PayloadWord { using type = uint32_t; };
+template <> struct PayloadWord<8> { using type = uint64_t; };
+template <int VB> using Pay = typename PayloadWord<VB>::type;
+
 template <class K> struct KeyTraits;
 template <> struct KeyTraits<uint32_t> {
   static constexpr uint32_t kMax = 0xFFFFFFFFu;
@@ -52,13 +59,13 @@ __device__ __forceinline__ void cx(uint64_t& a, uint64_t& b) {
 // strictly smaller (the paper's conditional swap), so equal keys never move
 // their values.  This strictness is what lets padding channels filled with
 // the maximum key stay in place (see pad_and_sort below).
-template <class K>
-__device__ __forceinline__ void cx_pair(K& a, K& b, uint32_t& va, uint32_t& vb) {
+template <class K, class VT>
+__device__ __forceinline__ void cx_pair(K& a, K& b, VT& va, VT& vb) {
   bool s = b < a;
   K lo = s ? b : a;
   K hi = s ? a : b;
-  uint32_t vlo = s ? vb : va;
-  uint32_t vhi = s ? va : vb;
+  VT vlo = s ? vb : va;
+  VT vhi = s ? va : vb;
   a = lo;
   b = hi;
   va = vlo;
@@ -69,9 +76,9 @@ template <class K, int N> struct KeyOp {
   K* r;
   __device__ __forceinline__ void operator()(int i, int j) { cx(r[i], r[j]); }
 };
-template <class K, int N> struct PairOp {
+template <class K, int N, class VT> struct PairOp {
   K* r;
-  uint32_t* v;
+  VT* v;
   __device__ __forceinline__ void operator()(int i, int j) { cx_pair(r[i], r[j], v[i], v[j]); }
 };
 
@@ -87,12 +94,12 @@ __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
 // dynamic register indexing); the inner loop ends as soon as no lane of the
 // wave is still shifting, so an already sorted input costs one compare per
 // key, as on the CPU, and the cost of a wave is that of its slowest lane.
-template <int N, class K, bool V>
-__device__ __forceinline__ void insertion_sort_regs(K (&r)[N], uint32_t* v) {
+template <int N, class K, bool V, class VT>
+__device__ __forceinline__ void insertion_sort_regs(K (&r)[N], VT* v) {
 #pragma unroll
   for (int i = 1; i < N; ++i) {
     const K x = r[i];
-    uint32_t xv = 0;
+    VT xv = 0;
     if constexpr (V) xv = v[i];
     bool go = true;  // this lane has not placed x yet
 #pragma unroll
@@ -114,18 +121,18 @@ __device__ __forceinline__ void insertion_sort_regs(K (&r)[N], uint32_t* v) {
 // Textbook insertion sort of one array of n keys (and values) in place in
 // global memory, by one lane: the larger-sets half of the paper's IS+SN
 // hybrid (Section 4.6: networks up to 16 keys, insertion sort above).  Keys
-// are compared after XOR with flip (the sign-bit map of signed keys).
-template <class K, bool V>
-__device__ __forceinline__ void insertion_sort_global(K* p, uint32_t* pv, int n, K flip) {
+// are compared as their order-preserving words (flip.enc).
+template <class K, int V>
+__device__ __forceinline__ void insertion_sort_global(K* p, Pay<V>* pv, int n, KeyMap<K> flip) {
   for (int i = 1; i < n; ++i) {
     const K xs = p[i];
-    const K x = xs ^ flip;
-    uint32_t xv = 0;
+    const K x = flip.enc(xs);
+    Pay<V> xv = 0;
     if constexpr (V) xv = pv[i];
     int j = i - 1;
     while (j >= 0) {
       const K ys = p[j];
-      if (!((ys ^ flip) > x)) break;
+      if (!(flip.enc(ys) > x)) break;
       p[j + 1] = ys;
       if constexpr (V) pv[j + 1] = pv[j];
       --j;
@@ -140,18 +147,18 @@ __device__ __forceinline__ void insertion_sort_global(K* p, uint32_t* pv, int n,
 template <int F, int N, class K>
 __device__ __forceinline__ void net_sort(K (&r)[N]) {
   if constexpr (F == kFamilyInsertion) {
-    insertion_sort_regs<N, K, false>(r, nullptr);
+    insertion_sort_regs<N, K, false, uint32_t>(r, nullptr);
   } else {
     KeyOp<K, N> op{r};
     Net<F, N>::run(op);
   }
 }
-template <int F, int N, class K>
-__device__ __forceinline__ void net_sort(K (&r)[N], uint32_t (&v)[N]) {
+template <int F, int N, class K, class VT>
+__device__ __forceinline__ void net_sort(K (&r)[N], VT (&v)[N]) {
   if constexpr (F == kFamilyInsertion) {
-    insertion_sort_regs<N, K, true>(r, v);
+    insertion_sort_regs<N, K, true, VT>(r, v);
   } else {
-    PairOp<K, N> op{r, v};
+    PairOp<K, N, VT> op{r, v};
     Net<F, N>::run(op);
   }
 }

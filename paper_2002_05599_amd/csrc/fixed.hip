@@ -74,7 +74,7 @@ template <class K> __device__ __forceinline__ void lds_st(unsigned char* p, K v)
 
 template <int F, int N, class K>
 __global__ void __launch_bounds__(kTileThreads)
-fixed_tile_kernel(K* __restrict__ keys, int64_t count, K flip) {
+fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
   using L = TileLayout<N, K>;
   __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
   constexpr int kChunks = kTileThreads * N * L::E / 16;  // 16-byte chunks in a full tile
@@ -137,10 +137,10 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, K flip) {
       for (int j = 0; j < N; ++j) r[j] = lds_ld<K>(lds + L::elem_offset(t, j));
     }
 #pragma unroll
-    for (int j = 0; j < N; ++j) r[j] ^= flip;
+    for (int j = 0; j < N; ++j) r[j] = flip.enc(r[j]);
     net_sort<F, N>(r);
 #pragma unroll
-    for (int j = 0; j < N; ++j) r[j] ^= flip;
+    for (int j = 0; j < N; ++j) r[j] = flip.dec(r[j]);
     if constexpr (L::kVec) {
 #pragma unroll
       for (int k = 0; k < L::C; ++k) {
@@ -190,20 +190,20 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, K flip) {
 // One thread per array, direct global accesses: any stride, any alignment.
 template <int F, int N, class K>
 __global__ void __launch_bounds__(kTileThreads)
-fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, K flip) {
+fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, KeyMap<K> flip) {
   const int64_t a = (int64_t)blockIdx.x * kTileThreads + threadIdx.x;
   if (a >= count) return;
   K* p = keys + a * stride;
   K r[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) r[j] = p[j] ^ flip;
+  for (int j = 0; j < N; ++j) r[j] = flip.enc(p[j]);
   net_sort<F, N>(r);
 #pragma unroll
-  for (int j = 0; j < N; ++j) p[j] = r[j] ^ flip;
+  for (int j = 0; j < N; ++j) p[j] = flip.dec(r[j]);
 }
 
 template <int F, int N, class K>
-static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, K flip, hipStream_t s) {
+static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
   const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
@@ -218,7 +218,7 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, K flip,
 }
 
 template <int F, class K>
-static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
   switch (n) {
     case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, s);
     case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, s);
@@ -269,7 +269,7 @@ hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
                             hipStream_t s) {
   switch (tuning().family) {
     case 1: return launch_fixed_f<1>(keys, n, count, stride, flip, s);
@@ -277,7 +277,7 @@ hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride
     default: return launch_fixed_f<0>(keys, n, count, stride, flip, s);
   }
 }
-hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                             hipStream_t s) {
   switch (tuning().family) {
     case 1: return launch_fixed_f<1>(keys, n, count, stride, flip, s);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "keymap.hpp"
+
 namespace ss {
 
 // Variant choices, set by the autotuner through ss_set_tuning_value.
@@ -20,16 +22,16 @@ struct Tuning {
 };
 Tuning tuning();  // a consistent copy of the current settings
 
-// Fixed layout, n = 2..16 (networks).  flip = sign-bit mask (0 for unsigned).
-hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+// Fixed layout, n = 2..16 (networks).  flip = the key type's order-preserving map.
+hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
                             hipStream_t s);
-hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                             hipStream_t s);
 
 // Fixed layout, n = 17..256 (Register Sample Sort).
-hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
                                 int* status, hipStream_t s);
-hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                                 int* status, hipStream_t s);
 
 // Streaming device-to-device copy of `bytes` (the read-once / write-once
@@ -66,18 +68,19 @@ hipError_t noalloc_buffers(DeviceCtx* c, SegBuffers* out);
 // with *err set to a HIP error.
 DeviceCtx* device_ctx(hipError_t* err);
 
-// Segmented (CSR) sorting; returns an ss_status code.
+// Segmented (CSR) sorting; returns an ss_status code.  vals: NULL or a
+// payload of vbytes = 4 (uint32) or 8 (uint64, 64-bit keys only) per key.
 // mode: 0 persistent kernel from a cached graph, 1 persistent kernel launched
 // directly, 2 one plain launch per size class.
-int segmented_u32(DeviceCtx* c, uint32_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
-                  uint32_t flip, int mode, hipStream_t s);
-int segmented_u64(DeviceCtx* c, uint64_t* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
-                  uint64_t flip, int mode, hipStream_t s);
+int segmented_u32(DeviceCtx* c, uint32_t* keys, void* vals, int vbytes, const int32_t* offsets, int32_t nseg,
+                  KeyMap<uint32_t> flip, int mode, hipStream_t s);
+int segmented_u64(DeviceCtx* c, uint64_t* keys, void* vals, int vbytes, const int32_t* offsets, int32_t nseg,
+                  KeyMap<uint64_t> flip, int mode, hipStream_t s);
 // The same sorts with the persistent kernels launched directly on the given
 // buffers (no graph, no working-memory allocation): the no-allocation path.
-int segmented_direct_u32(DeviceCtx* c, const SegBuffers& b, uint32_t* keys, uint32_t* vals,
-                         const int32_t* offsets, int32_t nseg, uint32_t flip, hipStream_t s);
-int segmented_direct_u64(DeviceCtx* c, const SegBuffers& b, uint64_t* keys, uint32_t* vals,
-                         const int32_t* offsets, int32_t nseg, uint64_t flip, hipStream_t s);
+int segmented_direct_u32(DeviceCtx* c, const SegBuffers& b, uint32_t* keys, void* vals, int vbytes,
+                         const int32_t* offsets, int32_t nseg, KeyMap<uint32_t> flip, hipStream_t s);
+int segmented_direct_u64(DeviceCtx* c, const SegBuffers& b, uint64_t* keys, void* vals, int vbytes,
+                         const int32_t* offsets, int32_t nseg, KeyMap<uint64_t> flip, hipStream_t s);
 
 }  // namespace ss

@@ -12,28 +12,28 @@ constexpr int kRssWaves = kRssThreads / kWave;
 
 template <int F, class K, int G>
 __global__ void __launch_bounds__(kRssThreads)
-rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip, int k0, int level_cap) {
+rss_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, int k0, int level_cap) {
   constexpr int kGroups = kWave / G;
-  __shared__ GroupLds<K, false, G> lds[kRssWaves * kGroups];
+  __shared__ GroupLds<K, 0, G> lds[kRssWaves * kGroups];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
   const int g = lane_id() / G;
   const int64_t arr = ((int64_t)blockIdx.x * kRssWaves + wave) * kGroups + g;
   const int m = arr < count ? n : 0;
   K* gk = keys + (arr < count ? arr * stride : 0);
-  rss_group_sort<F, K, false, G>(lds[wave * kGroups + g], gk, nullptr, m, flip, k0, level_cap);
+  rss_group_sort<F, K, 0, G>(lds[wave * kGroups + g], gk, nullptr, m, flip, k0, level_cap);
 }
 
 // The IS+SN alternative for 17..256 keys: one lane per array, insertion sort
 // in global memory.
 template <class K>
 __global__ void __launch_bounds__(kRssThreads)
-is_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, K flip) {
+is_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, KeyMap<K> flip) {
   const int64_t arr = (int64_t)blockIdx.x * kRssThreads + threadIdx.x;
-  if (arr < count) insertion_sort_global<K, false>(keys + arr * stride, nullptr, n, flip);
+  if (arr < count) insertion_sort_global<K, 0>(keys + arr * stride, nullptr, n, flip);
 }
 
 template <class K>
-static hipError_t launch_is_fixed(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+static hipError_t launch_is_fixed(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
   const int64_t blocks = (count + kRssThreads - 1) / kRssThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(is_fixed_kernel<K>, dim3((unsigned)blocks), dim3(kRssThreads), 0, s, keys, n, count, stride,
@@ -42,7 +42,7 @@ static hipError_t launch_is_fixed(K* keys, int n, int64_t count, int64_t stride,
 }
 
 template <int F, class K, int G>
-static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, K flip, int k0,
+static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, int k0,
                                int level_cap, hipStream_t s) {
   constexpr int per_block = kRssWaves * (kWave / G);
   const int64_t blocks = (count + per_block - 1) / per_block;
@@ -53,14 +53,14 @@ static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, K 
 }
 
 template <int F, class K>
-static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, K flip, hipStream_t s) {
+static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
   const Tuning t = tuning();
   if (n <= 64) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], t.rss_level_cap, s);
   if (n <= 128) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], t.rss_level_cap, s);
   return launch_rss_g<F, K, 64>(keys, n, count, stride, flip, t.rss_k[2], t.rss_level_cap, s);
 }
 
-hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, uint32_t flip,
+hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
                                 int* status, hipStream_t s) {
   (void)status;
   if (n < 17 || n > kMaxN) return hipErrorInvalidValue;
@@ -71,7 +71,7 @@ hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t st
     default: return launch_rss_f<0>(keys, n, count, stride, flip, s);
   }
 }
-hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, uint64_t flip,
+hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                                 int* status, hipStream_t s) {
   (void)status;
   if (n < 17 || n > kMaxN) return hipErrorInvalidValue;

@@ -52,7 +52,7 @@ namespace ss {
 
 constexpr int kLevelCap = 8;
 
-template <class K, bool V, int G> struct GroupLds {
+template <class K, int V, int G> struct GroupLds {
   static constexpr int kCap = 4 * G;          // keys per array handled by a G-lane group
   static constexpr int kMaxPend = kCap / 17;  // buckets with more than 16 keys
   static constexpr int kMaxFin = kCap / 2;    // buckets with 2..16 keys
@@ -61,7 +61,7 @@ template <class K, bool V, int G> struct GroupLds {
   // entry doubles as the sink for stores that fall outside a bucket
   static constexpr int kPad = 17;
   K key[kCap + kPad];
-  uint32_t val[V ? kCap + kPad : 1];
+  Pay<V> val[V ? kCap + kPad : 1];
   // Per pending bucket b, 16 entries from b*16: its sorted sample, the count
   // (then offset) of each child and each child's pending index at the next
   // level (0xFF if none).  The first level has one bucket and may use up to
@@ -120,11 +120,11 @@ __device__ __forceinline__ int classify(K e, const K* spl) {
 // N-key window at the bucket start is read unconditionally (the arrays have
 // slack) and the channels beyond the bucket are replaced by the maximum key;
 // stores beyond the bucket go to the sink entry instead of being masked.
-template <int F, int N, class K, bool V, int G>
+template <int F, int N, class K, int V, int G>
 __device__ __forceinline__ void finish_buckets(GroupLds<K, V, G>& L, bool ok, int st, int sz) {
   using Lds = GroupLds<K, V, G>;
   K r[N];
-  uint32_t v[N];
+  Pay<V> v[N];
   const int n = ok ? sz : 0;
   const K* kp = &L.key[st];
 #pragma unroll
@@ -133,7 +133,7 @@ __device__ __forceinline__ void finish_buckets(GroupLds<K, V, G>& L, bool ok, in
     r[j] = j < n ? x : KeyTraits<K>::kMax;
   }
   if constexpr (V) {
-    const uint32_t* vp = &L.val[st];
+    const Pay<V>* vp = &L.val[st];
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = vp[j];
     net_sort<F, N>(r, v);
@@ -149,7 +149,7 @@ __device__ __forceinline__ void finish_buckets(GroupLds<K, V, G>& L, bool ok, in
   }
 }
 
-template <int F, class K, bool V, int G>
+template <int F, class K, int V, int G>
 __device__ __forceinline__ void finish_dispatch(GroupLds<K, V, G>& L, bool ok, int st, int sz, int nmax) {
   switch (nmax) {
     case 2: finish_buckets<F, 2>(L, ok, st, sz); break;
@@ -252,7 +252,7 @@ __device__ __forceinline__ K team_sort(K x, int t) {
 // per bucket, one key per lane, the T - NS spare lanes holding the maximum
 // key), sorted across the team; also clears the bucket's child counters and
 // records whether all of its k-1 splitters are equal.
-template <int KB, class K, bool V, int G>
+template <int KB, class K, int V, int G>
 __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
   constexpr int A = oversampling(KB);
   constexpr int NS = A * KB;
@@ -315,7 +315,7 @@ __device__ __forceinline__ int three_way(K e, K v) {
 // offsets, the children are registered (finish list or next-level pending
 // list, in position order) and every key is written to bucket start + child
 // offset + rank, together with its next-level bucket id.
-template <int LOGK, bool kFirst, class K, bool V, int G>
+template <int LOGK, bool kFirst, class K, int V, int G>
 __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
   constexpr int k = 1 << LOGK;
   constexpr int a = oversampling(k);
@@ -346,7 +346,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
   // (bucket, child) entry << 16 | its rank among that child's keys, or ~0 if
   // the key is not in a pending bucket
   K e[4];
-  uint32_t v[4];
+  Pay<V> v[4];
   uint32_t dst[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -357,7 +357,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     if (i < m) pp = kFirst ? (np > 0 ? 0 : 0xFF) : (int)L.pb[i];
     const bool ok = pp != 0xFF;
     e[s] = ok ? L.key[i] : K(0);
-    if constexpr (V) v[s] = ok ? L.val[i] : 0u;
+    if constexpr (V) v[s] = ok ? L.val[i] : Pay<V>(0);
     int cc;
     if constexpr (kRegTree) {
       cc = classify<LOGK>(e[s], spl);
@@ -437,7 +437,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
 }
 
 // Rank-counting sort of the remaining pending buckets (after kLevelCap levels).
-template <class K, bool V, int G>
+template <class K, int V, int G>
 __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur, int np) {
   const int gl = lane_id() % G;
   for (int p = 0; ballot(p < np) != 0ull; ++p) {
@@ -445,14 +445,14 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
     const int st = active ? (int)L.pend_st[cur][p] : 0;
     const int sz = active ? (int)L.pend_sz[cur][p] : 0;
     K e[4];
-    uint32_t v[4];
+    Pay<V> v[4];
     int rank[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = gl + G * s;
       const bool ok = active && i < sz;
       e[s] = ok ? L.key[st + i] : K(0);
-      if constexpr (V) v[s] = ok ? L.val[st + i] : 0u;
+      if constexpr (V) v[s] = ok ? L.val[st + i] : Pay<V>(0);
       rank[s] = 0;
     }
     const int jmax = (int)wave_max((uint32_t)sz);
@@ -482,7 +482,7 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
 // L.val), in place in LDS.  Every lane of the wave must call this (loops are
 // wave-uniform).  k0: first-level bucket count; level_cap (1..kLevelCap):
 // levels of sample sort before the rank-counting fallback.
-template <int F, class K, bool V, int G>
+template <int F, class K, int V, int G>
 __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0, int level_cap) {
   const int gl = lane_id() % G;
   int np = m > 16 ? 1 : 0;
@@ -551,28 +551,28 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
 }
 
 // Global -> LDS (keys XORed with flip), coalesced within the group.
-template <class K, bool V, int G>
-__device__ __forceinline__ void rss_group_load(GroupLds<K, V, G>& L, const K* gk, const uint32_t* gv, int m, K flip) {
+template <class K, int V, int G>
+__device__ __forceinline__ void rss_group_load(GroupLds<K, V, G>& L, const K* gk, const Pay<V>* gv, int m, KeyMap<K> flip) {
   const int gl = lane_id() % G;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int i = gl + G * s;
     if (i < m) {
-      L.key[i] = gk[i] ^ flip;
+      L.key[i] = flip.enc(gk[i]);
       if constexpr (V) L.val[i] = gv[i];
     }
   }
 }
 
 // LDS -> global (keys XORed with flip), coalesced within the group.
-template <class K, bool V, int G>
-__device__ __forceinline__ void rss_group_store(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip) {
+template <class K, int V, int G>
+__device__ __forceinline__ void rss_group_store(GroupLds<K, V, G>& L, K* gk, Pay<V>* gv, int m, KeyMap<K> flip) {
   const int gl = lane_id() % G;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int i = gl + G * s;
     if (i < m) {
-      gk[i] = L.key[i] ^ flip;
+      gk[i] = flip.dec(L.key[i]);
       if constexpr (V) gv[i] = L.val[i];
     }
   }
@@ -581,8 +581,8 @@ __device__ __forceinline__ void rss_group_store(GroupLds<K, V, G>& L, K* gk, uin
 // Loads, sorts and stores one array of m keys per G-lane group; gk/gv point at
 // the group's array in global memory; keys are XORed with flip on load and
 // store.
-template <int F, class K, bool V, int G>
-__device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, uint32_t* gv, int m, K flip, int k0,
+template <int F, class K, int V, int G>
+__device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, Pay<V>* gv, int m, KeyMap<K> flip, int k0,
                                                int level_cap) {
   rss_group_load(L, gk, gv, m, flip);
   wave_lds_sync();

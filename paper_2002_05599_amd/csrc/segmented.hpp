@@ -113,20 +113,20 @@ __device__ __forceinline__ int bin_class(int sz, int mix) {
 
 // --- tile handlers -----------------------------------------------------------
 
-template <int F, int N, class K, bool V>
-__device__ __forceinline__ void net_tile(K* __restrict__ keys, uint32_t* __restrict__ vals,
+template <int F, int N, class K, int V>
+__device__ __forceinline__ void net_tile(K* __restrict__ keys, Pay<V>* __restrict__ vals,
                                          const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
-                                         int list, int count, int first, K flip) {
+                                         int list, int count, int first, KeyMap<K> flip) {
   const int j = first + lane_id();
   if (j >= count) return;
   const int seg = ids[list + j];
   K* p = keys + offsets[seg];
   K r[N];
-  uint32_t v[N];
+  Pay<V> v[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) r[i] = p[i] ^ flip;
+  for (int i = 0; i < N; ++i) r[i] = flip.enc(p[i]);
   if constexpr (V) {
-    uint32_t* pv = vals + offsets[seg];
+    Pay<V>* pv = vals + offsets[seg];
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = pv[i];
     net_sort<F, N>(r, v);
@@ -136,12 +136,12 @@ __device__ __forceinline__ void net_tile(K* __restrict__ keys, uint32_t* __restr
     net_sort<F, N>(r);
   }
 #pragma unroll
-  for (int i = 0; i < N; ++i) p[i] = r[i] ^ flip;
+  for (int i = 0; i < N; ++i) p[i] = flip.dec(r[i]);
 }
 
-template <int F, class K, bool V>
-__device__ __forceinline__ void net_tile_dispatch(int n, K* keys, uint32_t* vals, const int32_t* offsets,
-                                                  const int32_t* ids, int list, int count, int first, K flip) {
+template <int F, class K, int V>
+__device__ __forceinline__ void net_tile_dispatch(int n, K* keys, Pay<V>* vals, const int32_t* offsets,
+                                                  const int32_t* ids, int list, int count, int first, KeyMap<K> flip) {
   switch (n) {
     case 2: net_tile<F, 2, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
     case 3: net_tile<F, 3, K, V>(keys, vals, offsets, ids, list, count, first, flip); break;
@@ -164,15 +164,15 @@ __device__ __forceinline__ void net_tile_dispatch(int n, K* keys, uint32_t* vals
 // One segment of n <= N keys in the channels 0..n-1 of an N-key network;
 // channels n.. hold the maximum key, which the strict compare-exchange never
 // moves, so channels 0..n-1 end sorted.
-template <int F, int N, class K, bool V>
-__device__ __forceinline__ void net_sort_padded(K* __restrict__ p, uint32_t* __restrict__ pv, int n, K flip) {
+template <int F, int N, class K, int V>
+__device__ __forceinline__ void net_sort_padded(K* __restrict__ p, Pay<V>* __restrict__ pv, int n, KeyMap<K> flip) {
   K r[N];
-  uint32_t v[N];
+  Pay<V> v[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) r[i] = i < n ? (p[i] ^ flip) : KeyTraits<K>::kMax;
+  for (int i = 0; i < N; ++i) r[i] = i < n ? flip.enc(p[i]) : KeyTraits<K>::kMax;
   if constexpr (V) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = i < n ? pv[i] : 0u;
+    for (int i = 0; i < N; ++i) v[i] = i < n ? pv[i] : Pay<V>(0);
     net_sort<F, N>(r, v);
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -182,7 +182,7 @@ __device__ __forceinline__ void net_sort_padded(K* __restrict__ p, uint32_t* __r
   }
 #pragma unroll
   for (int i = 0; i < N; ++i)
-    if (i < n) p[i] = r[i] ^ flip;
+    if (i < n) p[i] = flip.dec(r[i]);
 }
 
 // A tile of 64 segments of 2..16 keys of any sizes, in batch order (the
@@ -191,10 +191,10 @@ __device__ __forceinline__ void net_sort_padded(K* __restrict__ p, uint32_t* __r
 // Segments that are neighbours in memory are then read by the same wave at
 // the same time and share their cache lines, where per-size classes would
 // read each line once per class that touches it.
-template <int F, class K, bool V>
-__device__ __forceinline__ void net_tile_mixed(K* keys, uint32_t* vals, const int32_t* __restrict__ offsets,
+template <int F, class K, int V>
+__device__ __forceinline__ void net_tile_mixed(K* keys, Pay<V>* vals, const int32_t* __restrict__ offsets,
                                                const int32_t* __restrict__ ids, int list, int count, int first,
-                                               K flip) {
+                                               KeyMap<K> flip) {
   const int j = first + lane_id();
   int lo = 0, n = 0;
   if (j < count) {
@@ -204,7 +204,7 @@ __device__ __forceinline__ void net_tile_mixed(K* keys, uint32_t* vals, const in
   }
   const int nmax = (int)wave_max((uint32_t)n);
   K* p = keys + lo;
-  uint32_t* pv = V ? vals + lo : nullptr;
+  Pay<V>* pv = V ? vals + lo : nullptr;
   switch (nmax) {
     case 2: net_sort_padded<F, 2, K, V>(p, pv, n, flip); break;
     case 3: net_sort_padded<F, 3, K, V>(p, pv, n, flip); break;
@@ -225,7 +225,7 @@ __device__ __forceinline__ void net_tile_mixed(K* keys, uint32_t* vals, const in
 }
 
 // Per-wave LDS big enough for any RSS group layout of this key type.
-template <class K, bool V> struct WaveLds {
+template <class K, int V> struct WaveLds {
   static constexpr size_t kBytes16 = 4 * sizeof(GroupLds<K, V, 16>);
   static constexpr size_t kBytes32 = 2 * sizeof(GroupLds<K, V, 32>);
   static constexpr size_t kBytes64 = sizeof(GroupLds<K, V, 64>);
@@ -238,10 +238,10 @@ template <class K, bool V> struct WaveLds {
 // handed to the groups with lane permutes, and the next round's keys are
 // loaded into registers before the current round is sorted, so the sort
 // hides the load latency.
-template <int F, class K, bool V, int G>
-__device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint32_t* vals,
+template <int F, class K, int V, int G>
+__device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V>* vals,
                                          const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
-                                         int list, int count, int first, int rounds, K flip, int k0,
+                                         int list, int count, int first, int rounds, KeyMap<K> flip, int k0,
                                          int level_cap) {
   constexpr int kGroups = kWave / G;
   auto* L = reinterpret_cast<GroupLds<K, V, G>*>(wave_lds);
@@ -268,7 +268,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
   };
   const int gl = lane % G;
   K nk[4];
-  uint32_t nv[4];
+  Pay<V> nv[4];
   auto fetch = [&](int lo, int m) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -287,7 +287,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
     for (int s = 0; s < 4; ++s) {
       const int i = gl + G * s;
       if (i < m) {
-        L[g].key[i] = nk[s] ^ flip;
+        L[g].key[i] = flip.enc(nk[s]);
         if constexpr (V) L[g].val[i] = nv[s];
       }
     }
@@ -307,10 +307,10 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, uint3
 
 // The IS+SN alternative for the RSS classes: the tile's segments sorted one
 // per lane by insertion sort in global memory (64 segments per pass).
-template <class K, bool V>
-__device__ __forceinline__ void is_tile(K* keys, uint32_t* vals, const int32_t* __restrict__ offsets,
+template <class K, int V>
+__device__ __forceinline__ void is_tile(K* keys, Pay<V>* vals, const int32_t* __restrict__ offsets,
                                         const int32_t* __restrict__ ids, int list, int count, int first, int ntile,
-                                        K flip) {
+                                        KeyMap<K> flip) {
   for (int j0 = 0; j0 < ntile; j0 += kWave) {
     const int j = first + j0 + lane_id();
     if (j0 + lane_id() < ntile && j < count) {
@@ -351,9 +351,9 @@ __host__ __device__ __forceinline__ bool in_kind(int c, int ks) {
 
 // Runs tile `tile_in_class` of class c (only the handlers of kind set KS are
 // compiled in).
-template <int F, class K, bool V, int KS>
-__device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, uint32_t* vals, const SortArgs& a,
-                                         K flip, int c, int tile_in_class, int count, int list, int waves) {
+template <int F, class K, int V, int KS>
+__device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, Pay<V>* vals, const SortArgs& a,
+                                         KeyMap<K> flip, int c, int tile_in_class, int count, int list, int waves) {
   const int rounds = class_rounds(c, count, a.rounds, waves, kPersistTpw);
   const int first = tile_in_class * class_tile(c, rounds);
   if constexpr (KS == kKindAll || is_net_kind(KS)) {
@@ -443,7 +443,7 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
 // tiles need; the single-kind kernels keep their natural register count.
 // Register budget of the persistent kernels, as resident waves per SIMD
 // (VGPRs <= 512 / waves): the most each kind reaches without spilling.
-template <class K, bool V, int KS> struct PersistWaves {
+template <class K, int V, int KS> struct PersistWaves {
   static constexpr int kType = (sizeof(K) == 8 ? 2 : 0) + (V ? 1 : 0);  // u32, u32+v, u64, u64+v
   static constexpr int value = KS == kKindAll   ? (kType == 0 ? 5 : (kType == 3 ? 3 : 4))
                                : is_net_kind(KS) ? 1
@@ -452,7 +452,7 @@ template <class K, bool V, int KS> struct PersistWaves {
                                                                   : 4;
 };
 
-template <class K, bool V, int KS> struct PersistLds {
+template <class K, int V, int KS> struct PersistLds {
   static constexpr size_t kBytes = is_net_kind(KS)   ? 16
                                    : KS == kKindRss16 ? 4 * sizeof(GroupLds<K, V, 16>)
                                    : KS == kKindRss32 ? 2 * sizeof(GroupLds<K, V, 32>)
@@ -462,9 +462,9 @@ template <class K, bool V, int KS> struct PersistLds {
 
 // Persistent kernel over the classes of kind set KS: waves run tiles until all
 // are done.  A single-class kernel indexes its tiles directly.
-template <int F, class K, bool V, int KS>
+template <int F, class K, int V, int KS>
 __global__ void __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(PersistWaves<K, V, KS>::value)))
-seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, uint32_t* ctrl, K flip) {
+seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, uint32_t* ctrl, KeyMap<K> flip) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][PersistLds<K, V, KS>::kBytes];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
   const int waves = (int)gridDim.x * kSortWaves;
@@ -585,9 +585,9 @@ seg_persistent_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArg
 // kernel is specialised per handler (KIND 0: networks, 1..3: RSS with 16-,
 // 32-, 64-lane groups), so each launch carries only its own code and
 // registers.
-template <int F, class K, bool V, int KIND>
+template <int F, class K, int V, int KIND>
 __global__ void __launch_bounds__(kSortThreads)
-seg_class_kernel(K* __restrict__ keys, uint32_t* __restrict__ vals, SortArgs a, K flip, int c, int count,
+seg_class_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, KeyMap<K> flip, int c, int count,
                  int list) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[kSortWaves][KIND == 0 ? 16 : WaveLds<K, V>::kBytes];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: keeps its uses scalar
@@ -645,7 +645,7 @@ SegmentedCache* workspace_for(DeviceCtx* c, hipStream_t s);
 // `s` (caller holds ws->mu).
 hipError_t ensure_workspace(SegmentedCache* ws, int32_t nseg, hipStream_t s);
 
-template <int F, class K, bool V, int KS>
+template <int F, class K, int V, int KS>
 static int persistent_blocks(DeviceCtx* c) {
   int occ = tuning().persist_occ;
   if (occ <= 0) {
@@ -681,7 +681,7 @@ inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
 // The kernels of one call with their arguments, as launch parameter blocks:
 // count, scan, scatter, then either the persistent kernel over every class or
 // (split) the network-class kernel followed by the RSS-class kernel.
-template <int F, class K, bool V>
+template <int F, class K, int V>
 struct SegLaunch {
   // argument storage (addresses handed to HIP)
   const int32_t* offsets;
@@ -694,9 +694,9 @@ struct SegLaunch {
   const uint32_t* blockbase;
   int32_t* ids;
   K* keys;
-  uint32_t* vals;
+  Pay<V>* vals;
   SortArgs args;
-  K flip;
+  KeyMap<K> flip;
   int mix;  // binning mixes the network sizes (persistent forms only)
   void* p_count[5];
   void* p_scan[3];
@@ -713,7 +713,7 @@ struct SegLaunch {
     return (i == 3 && mix) ? kKindNetMix : order[i - 3];
   }
 
-  void fill(DeviceCtx* c, const SegBuffers& s, K* k, uint32_t* v, const int32_t* off, int32_t n, K fl) {
+  void fill(DeviceCtx* c, const SegBuffers& s, K* k, Pay<V>* v, const int32_t* off, int32_t n, KeyMap<K> fl) {
     offsets = off;
     nseg = n;
     blockhist = s.blockhist;
@@ -801,7 +801,7 @@ struct SegLaunch {
   }
 };
 
-template <int F, class K, bool V>
+template <int F, class K, int V>
 static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
   // resident waves of one per-class launch (largest RSS class kernel)
   int nb = 0;
@@ -841,9 +841,9 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
   return hipGetLastError();
 }
 
-template <int F, class K, bool V>
+template <int F, class K, int V>
 static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
-  const int key = ((((int)sizeof(K) * 2 + (V ? 1 : 0)) * 3 + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0);
+  const int key = ((((int)sizeof(K) * 16 + V) * 3 + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0);
   GraphEntry* g = nullptr;
   for (GraphEntry& ge : sc->graphs)
     if (ge.key == key && std::equal(ge.persist_blocks, ge.persist_blocks + kKinds, L.persist_blocks)) g = &ge;
@@ -875,7 +875,7 @@ static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream
   return hipGraphLaunch(g->exec, s);
 }
 
-template <int F, class K, bool V>
+template <int F, class K, int V>
 static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
   L.split = tuning().persist_split != 0;
   for (int& b : L.persist_blocks) b = 0;
@@ -890,9 +890,9 @@ static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
   }
 }
 
-template <int F, class K, bool V>
-int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg,
-                   K flip, int mode, hipStream_t s) {
+template <int F, class K, int V>
+int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, Pay<V>* vals, const int32_t* offsets, int32_t nseg,
+                   KeyMap<K> flip, int mode, hipStream_t s) {
   SegLaunch<F, K, V> L;
   init_launch(c, L);
   L.fill(c, ws->buffers(), keys, vals, offsets, nseg, flip);
@@ -909,69 +909,83 @@ int segmented_impl(DeviceCtx* c, SegmentedCache* ws, K* keys, uint32_t* vals, co
 
 // The no-allocation form: binning and persistent kernels launched directly on
 // caller-provided buffers (the fixed scratch array); no graph, no allocation.
-template <int F, class K, bool V>
-int segmented_direct_impl(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals, const int32_t* offsets,
-                          int32_t nseg, K flip, hipStream_t s) {
+template <int F, class K, int V>
+int segmented_direct_impl(DeviceCtx* c, const SegBuffers& b, K* keys, Pay<V>* vals, const int32_t* offsets,
+                          int32_t nseg, KeyMap<K> flip, hipStream_t s) {
   SegLaunch<F, K, V> L;
   init_launch(c, L);
   L.fill(c, b, keys, vals, offsets, nseg, flip);
   return L.launch_direct(s) == hipSuccess ? 0 : -4;
 }
 
-// Every (family, key width, payload) combination of the segmented path.  Each
-// is compiled in an instantiation unit of its own (written by the build into
-// _build/, one explicit instantiation per unit, so the units compile in
-// parallel); every other unit only refers to them.
-#define SS_SEGMENTED_COMBOS(X)                                                                   \
-  X(0, uint32_t, false) X(0, uint32_t, true) X(1, uint32_t, false) X(1, uint32_t, true)          \
-  X(2, uint32_t, false) X(2, uint32_t, true) X(0, uint64_t, false) X(0, uint64_t, true)          \
-  X(1, uint64_t, false) X(1, uint64_t, true) X(2, uint64_t, false) X(2, uint64_t, true)
+// Every (family, key width, payload bytes) combination of the segmented path
+// (32-bit keys carry no payload or a 32-bit one; 64-bit keys also a 64-bit
+// one, the key + reference pairs of Section 2.2).  Each is compiled in an
+// instantiation unit of its own (written by the build into _build/, so the
+// units compile in parallel); every other unit only refers to them.
+#define SS_SEGMENTED_COMBOS(X)                                                                \
+  X(0, uint32_t, 0) X(0, uint32_t, 4) X(1, uint32_t, 0) X(1, uint32_t, 4) X(2, uint32_t, 0)   \
+  X(2, uint32_t, 4) X(0, uint64_t, 0) X(0, uint64_t, 4) X(0, uint64_t, 8) X(1, uint64_t, 0)   \
+  X(1, uint64_t, 4) X(1, uint64_t, 8) X(2, uint64_t, 0) X(2, uint64_t, 4) X(2, uint64_t, 8)
 
 #define SS_SEGMENTED_DECLARE(F, K, V, EXT)                                                              \
-  EXT template int segmented_impl<F, K, V>(DeviceCtx*, SegmentedCache*, K*, uint32_t*, const int32_t*, \
-                                           int32_t, K, int, hipStream_t);                               \
-  EXT template int segmented_direct_impl<F, K, V>(DeviceCtx*, const SegBuffers&, K*, uint32_t*,        \
-                                                  const int32_t*, int32_t, K, hipStream_t);
+  EXT template int segmented_impl<F, K, V>(DeviceCtx*, SegmentedCache*, K*, Pay<V>*, const int32_t*,   \
+                                           int32_t, KeyMap<K>, int, hipStream_t);                       \
+  EXT template int segmented_direct_impl<F, K, V>(DeviceCtx*, const SegBuffers&, K*, Pay<V>*,          \
+                                                  const int32_t*, int32_t, KeyMap<K>, hipStream_t);
 #define SS_SEGMENTED_EXTERN(F, K, V) SS_SEGMENTED_DECLARE(F, K, V, extern)
 #ifndef SS_SEGMENTED_INSTANCE_UNIT
 SS_SEGMENTED_COMBOS(SS_SEGMENTED_EXTERN)
 #endif
 
+// The instantiation for family F and the payload width: vbytes = 0 (no
+// payload), 4 or 8 (64-bit keys only).
+template <int F, class K>
+static int segmented_pick(DeviceCtx* c, SegmentedCache* ws, const SegBuffers* b, K* keys, void* vals, int vbytes,
+                          const int32_t* offsets, int32_t nseg, KeyMap<K> flip, int mode, hipStream_t s) {
+  if (vbytes == 8) {
+    if constexpr (sizeof(K) == 8) {
+      auto* v = static_cast<uint64_t*>(vals);
+      return b ? segmented_direct_impl<F, K, 8>(c, *b, keys, v, offsets, nseg, flip, s)
+               : segmented_impl<F, K, 8>(c, ws, keys, v, offsets, nseg, flip, mode, s);
+    }
+    return -1;
+  }
+  if (vbytes == 4) {
+    auto* v = static_cast<uint32_t*>(vals);
+    return b ? segmented_direct_impl<F, K, 4>(c, *b, keys, v, offsets, nseg, flip, s)
+             : segmented_impl<F, K, 4>(c, ws, keys, v, offsets, nseg, flip, mode, s);
+  }
+  return b ? segmented_direct_impl<F, K, 0>(c, *b, keys, nullptr, offsets, nseg, flip, s)
+           : segmented_impl<F, K, 0>(c, ws, keys, nullptr, offsets, nseg, flip, mode, s);
+}
+
 template <class K>
-static int segmented_any(DeviceCtx* c, K* keys, uint32_t* vals, const int32_t* offsets, int32_t nseg, K flip,
-                         int mode, hipStream_t s) {
+static int segmented_family(DeviceCtx* c, SegmentedCache* ws, const SegBuffers* b, K* keys, void* vals, int vbytes,
+                            const int32_t* offsets, int32_t nseg, KeyMap<K> flip, int mode, hipStream_t s) {
+  switch (tuning().family) {
+    case 1: return segmented_pick<1, K>(c, ws, b, keys, vals, vbytes, offsets, nseg, flip, mode, s);
+    case kFamilyInsertion:
+      return segmented_pick<kFamilyInsertion, K>(c, ws, b, keys, vals, vbytes, offsets, nseg, flip, mode, s);
+    default: return segmented_pick<0, K>(c, ws, b, keys, vals, vbytes, offsets, nseg, flip, mode, s);
+  }
+}
+
+template <class K>
+static int segmented_any(DeviceCtx* c, K* keys, void* vals, int vbytes, const int32_t* offsets, int32_t nseg,
+                         KeyMap<K> flip, int mode, hipStream_t s) {
   SegmentedCache* ws = workspace_for(c, s);
   if (!ws) return -5;
   std::lock_guard<std::mutex> lock(ws->mu);
   hipError_t e = ensure_workspace(ws, nseg, s);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? -5 : -4;
-  switch (tuning().family) {
-    case 1:
-      return vals ? segmented_impl<1, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
-                  : segmented_impl<1, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
-    case kFamilyInsertion:
-      return vals ? segmented_impl<kFamilyInsertion, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
-                  : segmented_impl<kFamilyInsertion, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
-    default:
-      return vals ? segmented_impl<0, K, true>(c, ws, keys, vals, offsets, nseg, flip, mode, s)
-                  : segmented_impl<0, K, false>(c, ws, keys, vals, offsets, nseg, flip, mode, s);
-  }
+  return segmented_family<K>(c, ws, nullptr, keys, vals, vbytes, offsets, nseg, flip, mode, s);
 }
 
 template <class K>
-static int segmented_direct_any(DeviceCtx* c, const SegBuffers& b, K* keys, uint32_t* vals,
-                                const int32_t* offsets, int32_t nseg, K flip, hipStream_t s) {
-  switch (tuning().family) {
-    case 1:
-      return vals ? segmented_direct_impl<1, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
-                  : segmented_direct_impl<1, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
-    case kFamilyInsertion:
-      return vals ? segmented_direct_impl<kFamilyInsertion, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
-                  : segmented_direct_impl<kFamilyInsertion, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
-    default:
-      return vals ? segmented_direct_impl<0, K, true>(c, b, keys, vals, offsets, nseg, flip, s)
-                  : segmented_direct_impl<0, K, false>(c, b, keys, vals, offsets, nseg, flip, s);
-  }
+static int segmented_direct_any(DeviceCtx* c, const SegBuffers& b, K* keys, void* vals, int vbytes,
+                                const int32_t* offsets, int32_t nseg, KeyMap<K> flip, hipStream_t s) {
+  return segmented_family<K>(c, nullptr, &b, keys, vals, vbytes, offsets, nseg, flip, 1, s);
 }
 
 }  // namespace ss

@@ -49,12 +49,37 @@ def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
 
 
 def random_keys(dtype, count: int, seed: int) -> np.ndarray:
-    """Uniform keys over the full range of ``dtype`` (u32/i32/u64/i64)."""
+    """Uniform keys over the full range of ``dtype`` (u32/i32/u64/i64); for
+    float32/float64, uniformly random bit patterns (every class of value:
+    normal, subnormal, zeros, infinities and NaNs of both signs)."""
     dt = np.dtype(dtype)
     w = splitmix64(seed, count)
     if dt.itemsize == 4:
         return (w >> np.uint64(32)).astype(np.uint32).view(dt)
     return w.view(dt)
+
+
+def float_keys(dtype, count: int, seed: int) -> np.ndarray:
+    """Float keys for the tests: 60% values spread over many magnitudes (a
+    sign, a 53-bit fraction and a power of two in [2^-40, 2^40]), 35% random
+    bit patterns (every class of value), 5% special values (+-0, +-inf,
+    +-NaN, +-1), which also makes duplicates."""
+    dt = np.dtype(dtype)
+    w = splitmix64(seed, 3 * count).reshape(3, count) if count else np.zeros((3, 0), np.uint64)
+    frac = (w[0] >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+    mag = np.ldexp(0.5 + frac / 2, ((w[1] >> np.uint64(58)).astype(np.int64) - 32) * 5 // 4)
+    vals = np.where((w[1] & np.uint64(1)) == 1, -mag, mag).astype(dt)
+    if dt.itemsize == 4:
+        bits = (w[2] >> np.uint64(32)).astype(np.uint32).view(dt)
+    else:
+        bits = w[2].view(dt)
+    pick = (w[2] % np.uint64(100)).astype(np.int64)
+    specials = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, -np.nan, 1.0, -1.0], dtype=dt)
+    specials[5] = np.copysign(specials[4], -1.0)
+    out = np.where(pick < 60, vals, bits)
+    sp = pick >= 95
+    out[sp] = specials[(w[0][sp] % np.uint64(8)).astype(np.int64)]
+    return np.ascontiguousarray(out.astype(dt))
 
 
 def fixed_keys(dtype, n: int, count: int, dist: str, seed: int) -> np.ndarray:

@@ -165,8 +165,98 @@ def pin_segments(lib):
             assert (vv[lo:hi] == v[lo:hi][order]).all(), f"segment payload {i}"
 
 
+# --- float keys (IEEE 754 totalOrder) and 64-bit payloads ------------------
+
+FLOATS = [np.float32, np.float64]
+
+
+def _finite_floats(dt, size, rng):
+    """Finite values over many magnitudes, both signs, no -0.0 and no NaN."""
+    x = rng.standard_normal(size) * np.exp2(rng.integers(-60, 60, size=size))
+    x = x.astype(dt)
+    x[x == 0] = dt(1.0)
+    return x
+
+
+def pin_float_vs_numpy(lib):
+    """Without signed zeros and NaNs, totalOrder is the order of the float
+    compare: numpy's sort."""
+    rng = np.random.default_rng(RNG_SEED + 5)
+    for dt in FLOATS:
+        for n in list(range(0, 20)) + [31, 64, 65, 129, 256]:
+            a = _finite_floats(dt, n, rng)
+            if n > 3:
+                a[rng.integers(0, n, size=2)] = [np.inf, -np.inf]
+            want = np.sort(a, kind="stable")
+            for f in (oracle.insertion_sort, oracle.merge_sort, oracle.sort_one):
+                assert (f(a, lib=lib)[0] == want).all(), f"{dt.__name__} n={n} {f.__name__}"
+        count, n = 50, 12
+        a = _finite_floats(dt, count * n, rng)
+        got = oracle.sort_fixed(a, n, count, n, lib=lib).reshape(count, n)
+        assert (got == np.sort(a.reshape(count, n), axis=1)).all()
+
+
+def pin_float_signed_zeros_and_infinities(lib):
+    """Every word of length <= 4 over special values against Python's sorted,
+    with -0.0 placed before +0.0 (the float value, then the sign of the zero)."""
+    import math
+    specials = [-np.inf, -2.5, -0.0, 0.0, 1.0, np.inf]
+    key = lambda x: (x, math.copysign(1.0, x))  # noqa: E731
+    for dt in FLOATS:
+        for n in range(1, 5):
+            for w in itertools.product(specials, repeat=n):
+                want = sorted(w, key=key)
+                a = np.array(w, dtype=dt)
+                for f in (oracle.insertion_sort, oracle.merge_sort, oracle.sort_one):
+                    got = f(a, lib=lib)[0]
+                    assert [(float(x), math.copysign(1.0, x)) for x in got] == [key(x) for x in want], \
+                        f"{dt.__name__} {w} via {f.__name__}"
+
+
+def pin_float_nans_at_the_ends(lib):
+    """NaNs with the sign bit set come first, the others last; the finite
+    middle is in float order."""
+    rng = np.random.default_rng(RNG_SEED + 6)
+    for dt in FLOATS:
+        for n in (5, 16, 40, 200):
+            a = _finite_floats(dt, n, rng)
+            pos = rng.choice(n, size=4, replace=False)
+            a[pos[:2]] = np.nan
+            a[pos[2:]] = -np.nan if np.signbit(-np.nan) else np.copysign(np.nan, -1.0)
+            for f in (oracle.insertion_sort, oracle.merge_sort, oracle.sort_one):
+                k = f(a, lib=lib)[0]
+                assert np.isnan(k[:2]).all() and np.signbit(k[:2]).all(), f"{dt.__name__} n={n} head"
+                assert np.isnan(k[-2:]).all() and not np.signbit(k[-2:]).any(), f"{dt.__name__} n={n} tail"
+                mid = k[2:-2]
+                assert (mid == np.sort(a[~np.isnan(a)])).all(), f"{dt.__name__} n={n} middle"
+
+
+def pin_payload_64(lib):
+    """A 64-bit payload (key + reference items) follows its key, all 64 bits."""
+    rng = np.random.default_rng(RNG_SEED + 7)
+    for dt in (np.uint64, np.int64, np.float64):
+        for n in (2, 9, 16, 17, 100, 256):
+            a = (_rand(dt, n, rng) if dt != np.float64 else _finite_floats(dt, n, rng))
+            v = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+            order = np.argsort(a, kind="stable")
+            for f in (oracle.insertion_sort, oracle.merge_sort, oracle.sort_one):
+                k, vv = f(a, v, lib=lib)
+                assert vv.dtype == np.uint64
+                assert (k == a[order]).all() and (vv == v[order]).all(), f"{dt.__name__} n={n} {f.__name__}"
+        off = np.array([0, 3, 3, 20, 21, 60], dtype=np.int32)
+        a = _rand(np.uint64, 60, rng)
+        v = rng.integers(0, 2**64, size=60, dtype=np.uint64, endpoint=False)
+        k, vv = oracle.sort_segments(a, off, v, lib=lib)
+        for i in range(off.size - 1):
+            lo, hi = off[i], off[i + 1]
+            order = np.argsort(a[lo:hi], kind="stable")
+            assert (k[lo:hi] == a[lo:hi][order]).all() and (vv[lo:hi] == v[lo:hi][order]).all()
+
+
 PINS = [pin_permutations, pin_small_words, pin_extremes, pin_random_vs_numpy,
-        pin_payload_stable, pin_permutation_product, pin_fixed_stride, pin_segments]
+        pin_payload_stable, pin_permutation_product, pin_fixed_stride, pin_segments,
+        pin_float_vs_numpy, pin_float_signed_zeros_and_infinities, pin_float_nans_at_the_ends,
+        pin_payload_64]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=lambda p: p.__name__)
@@ -189,11 +279,11 @@ def test_threaded_driver_matches_serial():
 
 MUTANTS = {
     # insertion sort: moves equal keys (breaks stability of the payload)
-    "is_nonstrict": ("while (j > 0 && keys[j - 1] > k)", "while (j > 0 && keys[j - 1] >= k)"),
+    "is_nonstrict": ("while (j > 0 && LT(k, keys[j - 1]))", "while (j > 0 && !LT(keys[j - 1], k))"),
     # insertion sort: never considers position 0
-    "is_off_by_one": ("while (j > 0 && keys[j - 1] > k)", "while (j > 1 && keys[j - 1] > k)"),
+    "is_off_by_one": ("while (j > 0 && LT(k, keys[j - 1]))", "while (j > 1 && LT(k, keys[j - 1]))"),
     # merge: wrong comparison direction
-    "merge_sign": ("if (keys[b] < keys[a])", "if (keys[b] > keys[a])"),
+    "merge_sign": ("if (LT(keys[b], keys[a]))", "if (LT(keys[a], keys[b]))"),
     # merge: drops the tail of the right run
     "merge_drop_tail": ("while (b < hi)  { tk[o] = keys[b];", "while (0)  { tk[o] = keys[b];"),
     # merge: payload taken from the wrong run
@@ -205,7 +295,19 @@ MUTANTS = {
     # segments: end taken from the wrong offset
     "segment_end": ("hi = offsets[i + 1];", "hi = offsets[i + 1] - 1;"),
     # unsigned keys compared as signed (an easy slip when stamping types)
-    "u32_as_i32": ("ORACLE_DEFINE(uint32_t, u32)", "ORACLE_DEFINE(int32_t, u32)"),
+    "u32_as_i32": ("ORACLE_DEFINE(uint32_t, u32, uint32_t, lt_u32)", "ORACLE_DEFINE(int32_t, u32, uint32_t, lt_i32)"),
+    # floats: the native compare (signed zeros equal, NaNs unordered)
+    "f32_native_compare": ("static inline int lt_f32(float a, float b) {",
+                           "static inline int lt_f32(float a, float b) { return a < b;"),
+    # floats: negatives ordered by ascending magnitude (raw sign-magnitude bits)
+    "f64_negatives_unreversed": ("    if (sx != sy) return sx > sy;\n    return sx ? mx > my : mx < my;\n}\n\n/* One",
+                                 "    if (sx != sy) return sx > sy;\n    return mx < my;\n}\n\n/* One"),
+    # floats: positive before negative
+    "f32_sign_order": ("    if (sx != sy) return sx > sy;      /* sign set first */",
+                       "    if (sx != sy) return sx < sy;      /* sign set first */"),
+    # the 64-bit payload stamped as a 32-bit one (payload halves lost)
+    "v64_as_v32": ("ORACLE_DEFINE(uint64_t, u64_v64, uint64_t, lt_u64)",
+                   "ORACLE_DEFINE(uint64_t, u64_v64, uint32_t, lt_u64)"),
 }
 
 
