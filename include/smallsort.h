@@ -6,7 +6,10 @@
  * Marianczuk, Sanders).  Arrays of 2..16 keys are sorted by branch-free
  * comparator networks held in registers (Section 2); arrays of 17..256 keys by
  * Register Sample Sort (Section 3), which splits them with sampled splitters
- * into buckets of at most 16 keys that are finished by networks.
+ * into buckets of at most 16 keys that are finished by networks; arrays of
+ * 257..4096 keys by one work-group each, which sorts runs of 256 keys with
+ * Register Sample Sort and merges them (the merge-sort use of the small
+ * sorters that Section 5 proposes).
  *
  * Conventions shared by every call:
  *   - All pointers to keys, values and offsets are DEVICE pointers (memory from
@@ -30,7 +33,7 @@
  *     payload of equal keys is only defined as a multiset.
  *   - Return values are ss_status codes; SS_OK is 0, errors are negative.
  *     Argument errors are detected on the host before anything is enqueued.
- *     Errors that depend on device data (a segment longer than 256 keys, a
+ *     Errors that depend on device data (a segment longer than 4096 keys, a
  *     decreasing offset) are recorded in a per-device status word, read with
  *     ss_device_status; the affected segment is left unsorted.
  *   - Working memory of the segmented path (counters, size-class lists,
@@ -66,7 +69,8 @@ typedef int32_t ss_status;
 #define SS_ESCRATCH (-7)  /* batch larger than the no-allocation entry point's scratch */
 
 #define SS_MAX_NETWORK_N 16   /* largest array sorted by a network alone */
-#define SS_MAX_N        256   /* largest array or segment */
+#define SS_MAX_RSS_N    256   /* largest array sorted by Register Sample Sort alone */
+#define SS_MAX_N       4096   /* largest array or segment */
 
 /* Key type codes for the generic entry points. */
 #define SS_KEY_U32 0
@@ -85,12 +89,13 @@ typedef int32_t ss_status;
  * Fixed layout (Sections 2 and 3; the ArrayInRow arrangement of Section 4.1):
  * array i occupies keys[i*stride, i*stride + n) for 0 <= i < count.  Entries
  * [n, stride) of each row are neither read nor written.
- *   n:      0..256.  n <= 1 or count == 0 is a no-op returning SS_OK.
+ *   n:      0..4096.  n <= 1 or count == 0 is a no-op returning SS_OK.
  *           2..16 use one comparator network per array; 17..256 use
- *           Register Sample Sort.
+ *           Register Sample Sort; 257..4096 one work-group per array (runs of
+ *           256 keys by Register Sample Sort, merged in LDS).
  *   stride: >= n (in keys).  count * stride keys must be addressable.
  * Errors: SS_EINVAL for n < 0, count < 0, stride < n or keys == NULL with
- * count > 0; SS_ETOOBIG for n > 256; SS_EALIGN if keys is not aligned to the
+ * count > 0; SS_ETOOBIG for n > 4096; SS_EALIGN if keys is not aligned to the
  * key size; SS_EHIP if a launch fails.
  */
 ss_status sort_small_u32(uint32_t *keys, int32_t n, int64_t count, int64_t stride, void *stream);
@@ -103,14 +108,15 @@ ss_status sort_small_f64(double *keys, int32_t n, int64_t count, int64_t stride,
 /*
  * Segmented layout (CSR): segment i is [offsets[i], offsets[i+1]) for
  * 0 <= i < nseg; `offsets` is a device int32 array of nseg+1 non-decreasing
- * entries (offsets[0] need not be 0).  Segment sizes 0..256; sizes 0 and 1
+ * entries (offsets[0] need not be 0).  Segment sizes 0..4096; sizes 0 and 1
  * are no-ops.  The batch is binned by segment size (Section 5's proposal of
  * solving base cases in batches of equal size) and sorted by one persistent
- * launch: networks for 2..16 keys, Register Sample Sort for 17..256.
+ * launch: networks for 2..16 keys, Register Sample Sort for 17..256, one
+ * work-group per segment of 257..4096 keys.
  *   vals: NULL (keys only) or a device uint32 array indexed like keys.
  * Errors: SS_EINVAL for nseg < 0 or a NULL pointer with nseg > 0; SS_EALIGN
  * for misaligned pointers; SS_ENOMEM / SS_EHIP from working memory or
- * launches.  Segments longer than 256 keys or with decreasing offsets are
+ * launches.  Segments longer than 4096 keys or with decreasing offsets are
  * skipped and flagged in the device status word (SS_ETOOBIG / SS_EINVAL).
  */
 ss_status segmented_sort_u32(uint32_t *keys, uint32_t *vals, const int32_t *offsets, int32_t nseg, void *stream);

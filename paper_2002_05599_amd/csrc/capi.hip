@@ -88,6 +88,13 @@ static ss_status sort_small(void* keys_v, int32_t n, int64_t count, int64_t stri
       herr = launch_fixed_u64(keys, n, count, stride, map, s);
     return from_hip(herr);
   }
+  if (n > SS_MAX_RSS_N) {
+    if constexpr (sizeof(W) == 4)
+      herr = launch_large_fixed_u32(keys, n, count, stride, map, s);
+    else
+      herr = launch_large_fixed_u64(keys, n, count, stride, map, s);
+    return from_hip(herr);
+  }
   DeviceCtx* c = device_ctx(&herr);
   if (!c) return from_hip(herr);
   if constexpr (sizeof(W) == 4)
@@ -295,7 +302,7 @@ const char* ss_strerror(ss_status status) {
     case SS_OK: return "success";
     case SS_EINVAL: return "invalid argument (size, count, stride, pointer or offsets)";
     case SS_EALIGN: return "pointer not aligned to its element size";
-    case SS_ETOOBIG: return "array or segment longer than 256 keys";
+    case SS_ETOOBIG: return "array or segment longer than 4096 keys";
     case SS_EHIP: return "HIP runtime error";
     case SS_ENOMEM: return "out of device memory";
     case SS_ENOTUNE: return "unknown tuning parameter or unreadable tuning file";

@@ -34,6 +34,12 @@ hipError_t launch_rss_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t st
 hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                                 int* status, hipStream_t s);
 
+// Fixed layout, n = 257..4096 (runs sorted by RSS, merged in LDS).
+hipError_t launch_large_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
+                                  hipStream_t s);
+hipError_t launch_large_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
+                                  hipStream_t s);
+
 // Streaming device-to-device copy of `bytes` (the read-once / write-once
 // ceiling the sorting kernels are measured against).
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);

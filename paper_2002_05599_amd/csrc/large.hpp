@@ -1,0 +1,121 @@
+// Arrays of 257..4096 keys: one 256-thread work-group per array.
+//
+// Section 5 names merge sort with merging networks as the way to build on the
+// small sorters for larger inputs.  Here the array is cut into runs of 256
+// keys; each wave sorts its runs with Register Sample Sort (the same G = 64
+// group sort as the 129..256-key class), and the sorted runs are then merged
+// pairwise in LDS, doubling the run length each round (at most four rounds
+// for 4096 keys).  In a merge round every thread produces 16 consecutive
+// outputs: it finds where its first output's diagonal crosses the two runs by
+// a binary search (merge path; ties are taken from the left run first) and
+// then merges 16 items sequentially.
+//
+// LDS holds two buffers of kMaxLargeN items (keys as order-preserving words,
+// then payloads).  The second buffer also holds the waves' Register Sample
+// Sort state while the runs are sorted; it is free again for the merges.
+#pragma once
+
+#include "rss.hpp"
+
+namespace ss {
+
+constexpr int kLargeThreads = 256;
+constexpr int kMaxLargeN = 4096;
+constexpr int kRunN = 256;                               // keys per run (one G = 64 group)
+constexpr int kMergePer = kMaxLargeN / kLargeThreads;    // merge outputs per thread
+
+template <class K, int V> struct LargeLds {
+  static constexpr size_t kKeyBytes = (size_t)kMaxLargeN * sizeof(K);
+  static constexpr size_t kValBytes = V ? (size_t)kMaxLargeN * sizeof(Pay<V>) : 0;
+  static constexpr size_t kBufBytes = kKeyBytes + kValBytes;
+  static constexpr size_t kBytes = 2 * kBufBytes;
+  static_assert((kLargeThreads / kWave) * sizeof(GroupLds<K, V, 64>) <= kBufBytes,
+                "the run sorts' state must fit the second buffer");
+};
+
+// Sorts the m (<= kMaxLargeN) keys at gk (and payloads at gv) with the whole
+// work-group; every thread of the work-group must call this.
+template <int F, class K, int V>
+__device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv, int m, KeyMap<K> flip, int k0,
+                                           int level_cap) {
+  using LL = LargeLds<K, V>;
+  using VT = Pay<V>;
+  K* key_buf[2] = {reinterpret_cast<K*>(lds), reinterpret_cast<K*>(lds + LL::kBufBytes)};
+  VT* val_buf[2] = {reinterpret_cast<VT*>(lds + LL::kKeyBytes),
+                    reinterpret_cast<VT*>(lds + LL::kBufBytes + LL::kKeyBytes)};
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = lane_id();
+  auto* group = reinterpret_cast<GroupLds<K, V, 64>*>(lds + LL::kBufBytes) + wave;
+
+  // runs of 256 keys, run r by wave r mod 4
+  const int nruns = (m + kRunN - 1) / kRunN;
+  for (int r = wave; r < nruns; r += kLargeThreads / kWave) {
+    const int lo = r * kRunN;
+    const int len = min(kRunN, m - lo);
+    rss_group_load(*group, gk + lo, V ? gv + lo : nullptr, len, flip);
+    wave_lds_sync();
+    rss_group_sort_lds<F>(*group, len, k0, level_cap);
+    for (int i = lane; i < len; i += kWave) {
+      key_buf[0][lo + i] = group->key[i];
+      if constexpr (V) val_buf[0][lo + i] = group->val[i];
+    }
+    wave_lds_sync();
+  }
+  __syncthreads();
+
+  // merge rounds: runs of length L in buffer `cur` -> runs of 2L in the other
+  int cur = 0;
+  for (int L = kRunN; L < m; L *= 2) {
+    const K* sk = key_buf[cur];
+    const VT* sv = val_buf[cur];
+    K* dk = key_buf[cur ^ 1];
+    VT* dv = val_buf[cur ^ 1];
+    const int out0 = (int)threadIdx.x * kMergePer;
+    if (out0 < m) {
+      // the pair of runs holding this thread's outputs (2L is a multiple of kMergePer)
+      const int a0 = (out0 / (2 * L)) * (2 * L);
+      const int la = min(L, m - a0);
+      const int b0 = a0 + la;
+      const int lb = min(L, m - b0);
+      const int d = out0 - a0;
+      // merge path: i keys of the left run among the first d outputs
+      int lo = max(0, d - lb), hi = min(d, la);
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sk[a0 + mid] <= sk[b0 + d - 1 - mid])
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      int i = lo, j = d - lo;
+      const int n_out = min(kMergePer, la + lb - d);
+      for (int e = 0; e < n_out; ++e) {
+        const bool take_a = i < la && (j >= lb || sk[a0 + i] <= sk[b0 + j]);
+        const int src = take_a ? a0 + i : b0 + j;
+        dk[out0 + e] = sk[src];
+        if constexpr (V) dv[out0 + e] = sv[src];
+        i += take_a ? 1 : 0;
+        j += take_a ? 0 : 1;
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // store, mapping the words back to keys
+  for (int i = (int)threadIdx.x; i < m; i += kLargeThreads) {
+    gk[i] = flip.dec(key_buf[cur][i]);
+    if constexpr (V) gv[i] = val_buf[cur][i];
+  }
+  __syncthreads();
+}
+
+// Lets a kernel use `bytes` of dynamic LDS (above the default limit of the
+// launch); called once per kernel before its first launch.
+template <class Kernel>
+inline hipError_t allow_dynamic_lds(Kernel kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace ss

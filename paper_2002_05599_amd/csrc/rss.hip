@@ -3,6 +3,7 @@
 // waves; each wave sorts 64/G arrays at once, one per G-lane group, with
 // G = 16 for n <= 64, 32 for n <= 128 and 64 above (at most 4 keys per lane).
 #include "internal.hpp"
+#include "large.hpp"
 #include "rss.hpp"
 
 namespace ss {
@@ -81,6 +82,48 @@ hipError_t launch_rss_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t st
     case kFamilyInsertion: return launch_rss_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
     default: return launch_rss_f<0>(keys, n, count, stride, flip, s);
   }
+}
+
+// Arrays of 257..4096 keys: one work-group per array (large.hpp); with
+// large_sort = 1, insertion sort by one lane per array (IS+SN).
+template <int F, class K>
+__global__ void __launch_bounds__(kLargeThreads)
+large_fixed_kernel(K* __restrict__ keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, int k0, int level_cap) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char large_lds[];
+  for (int64_t arr = blockIdx.x; arr < count; arr += gridDim.x)
+    large_sort<F, K, 0>(large_lds, keys + arr * stride, nullptr, n, flip, k0, level_cap);
+}
+
+template <int F, class K>
+static hipError_t launch_large_f(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
+  const Tuning t = tuning();
+  constexpr size_t kLds = LargeLds<K, 0>::kBytes;
+  static const hipError_t attr = allow_dynamic_lds(large_fixed_kernel<F, K>, kLds);
+  if (attr != hipSuccess) return attr;
+  const int64_t blocks = count < (1 << 20) ? count : (1 << 20);
+  hipLaunchKernelGGL((large_fixed_kernel<F, K>), dim3((unsigned)blocks), dim3(kLargeThreads), kLds, s, keys, n,
+                     count, stride, flip, t.rss_k[2], t.rss_level_cap);
+  return hipGetLastError();
+}
+
+template <class K>
+static hipError_t launch_large_any(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
+  if (n <= kMaxN || n > kMaxLargeN) return hipErrorInvalidValue;
+  if (tuning().large_sort == 1) return launch_is_fixed(keys, n, count, stride, flip, s);
+  switch (tuning().family) {
+    case 1: return launch_large_f<1>(keys, n, count, stride, flip, s);
+    case kFamilyInsertion: return launch_large_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
+    default: return launch_large_f<0>(keys, n, count, stride, flip, s);
+  }
+}
+
+hipError_t launch_large_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
+                                  hipStream_t s) {
+  return launch_large_any(keys, n, count, stride, flip, s);
+}
+hipError_t launch_large_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
+                                  hipStream_t s) {
+  return launch_large_any(keys, n, count, stride, flip, s);
 }
 
 }  // namespace ss

@@ -22,9 +22,11 @@
 //            pieces at the end, so they finish together.  A single kernel for
 //            every class is kept as a tuning choice.
 //
-// Size classes: 0..14 = sizes 2..16, 15 = 17..64, 16 = 65..128, 17 = 129..256.
-// Sizes 0 and 1 need no work.  A segment longer than 256 keys or with a
-// negative size is skipped and flagged in the status word.
+// Size classes: 0..14 = sizes 2..16, 15 = 17..64, 16 = 65..128, 17 = 129..256,
+// 18 = 257..4096 (one work-group per segment: Register Sample Sort of runs of
+// 256 keys, then merge rounds in LDS, large.hpp).  Sizes 0 and 1 need no work.
+// A segment longer than 4096 keys or with a negative size is skipped and
+// flagged in the status word.
 //
 // Modes: the binning and persistent kernels replayed from a cached hipGraph
 // (built once per key type / payload / network family / kernel split; each
@@ -38,11 +40,14 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "large.hpp"
 #include "rss.hpp"
 
 namespace ss {
 
-constexpr int kClasses = 18;
+constexpr int kClasses = 19;       // size classes of the binning
+constexpr int kTiledClasses = 18;  // classes sorted in wave-sized tiles (networks, RSS)
+constexpr int kLargeClass = 18;    // 257..4096 keys: one work-group per segment
 constexpr int kNetClasses = 15;
 constexpr int kBinThreads = 256;
 constexpr int kBinItems = 4;                       // segments per thread per chunk
@@ -64,6 +69,7 @@ __device__ __forceinline__ int size_class(int sz) {
   if (sz <= 64) return 15;
   if (sz <= 128) return 16;
   if (sz <= kMaxN) return 17;
+  if (sz <= kMaxLargeN) return kLargeClass;
   return -2;  // too big
 }
 
@@ -422,10 +428,10 @@ __device__ __forceinline__ void locate_tile(int t, const uint32_t* ctrl, int rou
     list_pos = t;
   }
   // walk the classes in hand-out order (wave-uniform scalar loads)
-  cls = class_at(kClasses - 1);
+  cls = class_at(kTiledClasses - 1);
   idx = 0;
   int acc = 0;
-  for (int o = 0; o < kClasses; ++o) {
+  for (int o = 0; o < kTiledClasses; ++o) {
     const int c = class_at(o);
     const int n = class_tiles<KS>(ctrl, c, rounds, waves);
     if (list_pos < acc + n) {
@@ -520,7 +526,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
   }
   // tiles of the RSS classes and of the network classes (wave-uniform)
   int t_rss = 0, t_net = 0;
-  for (int c = 0; c < kClasses; ++c) {
+  for (int c = 0; c < kTiledClasses; ++c) {
     const int n = class_tiles<KS>(a.ctrl, c, a.rounds, waves);
     if (c >= kNetClasses)
       t_rss += n;
@@ -610,13 +616,49 @@ seg_class_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, Ke
   }
 }
 
+// Segments of 257..4096 keys: one work-group per segment, the work-groups
+// striding over the class list (the same kernel serves every form; the count
+// comes from the binning's control block).  With large_sort = 1 (the IS+SN
+// alternative) one lane per segment sorts it by insertion sort instead.
+template <int F, class K, int V>
+__global__ void __launch_bounds__(kLargeThreads)
+seg_large_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, KeyMap<K> flip) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char large_lds[];
+  const int count = (int)a.ctrl[kCtrlCount + kLargeClass];
+  const int list = (int)a.ctrl[kCtrlStart + kLargeClass];
+  for (int j = blockIdx.x; j < count; j += gridDim.x) {
+    const int seg = a.ids[list + j];
+    const int lo = a.offsets[seg];
+    const int m = a.offsets[seg + 1] - lo;
+    if (a.large_sort) {
+      if (threadIdx.x == 0) insertion_sort_global<K, V>(keys + lo, V ? vals + lo : nullptr, m, flip);
+      continue;
+    }
+    large_sort<F, K, V>(large_lds, keys + lo, V ? vals + lo : nullptr, m, flip, a.k0[2], a.level_cap);
+  }
+}
+
+// Work-groups of the large-class kernel: as many as are resident at once
+// (its dynamic LDS is raised above the default limit on first use).
+template <int F, class K, int V>
+static int large_blocks(DeviceCtx* c) {
+  static const hipError_t attr = allow_dynamic_lds(seg_large_kernel<F, K, V>, LargeLds<K, V>::kBytes);
+  int nb = 0;
+  if (attr != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_large_kernel<F, K, V>, kLargeThreads,
+                                                   LargeLds<K, V>::kBytes) != hipSuccess ||
+      nb <= 0)
+    nb = 1;
+  return nb * c->num_cus;
+}
+
 // --- host side ---------------------------------------------------------------
 
 struct GraphEntry {
   int key = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t nodes[7] = {};  // count, scan, scatter, then the persistent kernel(s)
+  hipGraphNode_t nodes[8] = {};  // count, scan, scatter, the persistent kernel(s), the large class
   int nnodes = 0;
   int persist_blocks[kKinds] = {};
 };
@@ -702,10 +744,12 @@ struct SegLaunch {
   void* p_scan[3];
   void* p_scatter[6];
   void* p_sort[5];
+  void* p_sort_large[4];
   bool split;
   int persist_blocks[kKinds];  // grid of the persistent kernel per kind set
+  int large_grid;              // work-groups of the large-class kernel
 
-  int nnodes() const { return split ? 7 : 4; }
+  int nnodes() const { return split ? 8 : 5; }
   // kind set of node i >= 3: network classes, then the RSS classes largest first
   int node_kind(int i) const {
     if (!split) return kKindAll;
@@ -733,6 +777,7 @@ struct SegLaunch {
     p_scatter[0] = &offsets; p_scatter[1] = &nseg; p_scatter[2] = &blockbase; p_scatter[3] = &ctrl_c;
     p_scatter[4] = &ids; p_scatter[5] = &mix;
     p_sort[0] = &keys; p_sort[1] = &vals; p_sort[2] = &args; p_sort[3] = &ctrl; p_sort[4] = &flip;
+    p_sort_large[0] = &keys; p_sort_large[1] = &vals; p_sort_large[2] = &args; p_sort_large[3] = &flip;
   }
 
   static void* kernel_of(int ks) {
@@ -770,6 +815,14 @@ struct SegLaunch {
         p.kernelParams = p_scatter;
         break;
       default: {
+        if (i == nnodes() - 1) {
+          p.func = (void*)seg_large_kernel<F, K, V>;
+          p.gridDim = dim3(large_grid);
+          p.blockDim = dim3(kLargeThreads);
+          p.sharedMemBytes = LargeLds<K, V>::kBytes;
+          p.kernelParams = p_sort_large;
+          break;
+        }
         const int ks = node_kind(i);
         p.func = kernel_of(ks);
         p.gridDim = dim3(persist_blocks[ks]);
@@ -794,7 +847,7 @@ struct SegLaunch {
     if (e != hipSuccess) return e;
     for (int i = 3; i < nnodes(); ++i) {
       hipKernelNodeParams p = node(i);
-      hipError_t le = hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, 0, s);
+      hipError_t le = hipLaunchKernel(p.func, p.gridDim, p.blockDim, p.kernelParams, p.sharedMemBytes, s);
       if (le != hipSuccess) return le;
     }
     return hipGetLastError();
@@ -817,7 +870,7 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
     e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, (kCtrlStart + kClasses) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
-  for (int o = 0; o < kClasses; ++o) {
+  for (int o = 0; o < kTiledClasses; ++o) {
     const int cls = class_at(o);
     const int count = (int)sc->host_ctrl[kCtrlCount + cls];
     if (count == 0) continue;
@@ -837,6 +890,13 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
     else
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 3>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
+  }
+  const int nlarge = (int)sc->host_ctrl[kCtrlCount + kLargeClass];
+  if (nlarge > 0) {
+    hipKernelNodeParams p = L.node(L.nnodes() - 1);
+    hipError_t le = hipLaunchKernel(p.func, dim3(min(nlarge, L.large_grid)), p.blockDim, p.kernelParams,
+                                    p.sharedMemBytes, s);
+    if (le != hipSuccess) return le;
   }
   return hipGetLastError();
 }
@@ -888,6 +948,7 @@ static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
   } else {
     L.persist_blocks[kKindAll] = persistent_blocks<F, K, V, kKindAll>(c);
   }
+  L.large_grid = large_blocks<F, K, V>(c);
 }
 
 template <int F, class K, int V>

@@ -49,8 +49,8 @@ def test_strerror_and_version(lib):
 
 def test_argument_errors_need_no_device(lib):
     p = ctypes.c_void_p(0x1000)
-    # n > 256, stride < n, negative sizes, misalignment: rejected on the host
-    assert lib.sort_small_u32(p, 257, 1, 257, None) == -3
+    # n > 4096, stride < n, negative sizes, misalignment: rejected on the host
+    assert lib.sort_small_u32(p, 4097, 1, 4097, None) == -3
     assert lib.sort_small_u32(p, 8, 1, 7, None) == -1
     assert lib.sort_small_u32(p, -1, 1, 8, None) == -1
     assert lib.sort_small_u32(p, 8, -5, 8, None) == -1

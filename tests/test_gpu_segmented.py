@@ -99,7 +99,7 @@ def test_config4_shape_small_all_modes_agree():
 
 
 def test_oversize_and_bad_offsets_flagged():
-    sizes = np.array([5, 300, 20, 0, 1, 256])
+    sizes = np.array([5, 4097, 20, 0, 1, 256, 300])
     off = inputs.offsets_from_sizes(sizes)
     keys = inputs.random_keys(np.uint32, int(off[-1]), seed=1)
     got, _ = run_seg(keys, off)
