@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="all",
                    choices=["all", "fixed16_u32", "copy", "config1", "config2", "rss", "rss_classes", "ragged",
-                            "serve", "is_vs_sn"])
+                            "serve", "is_vs_sn", "large"])
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extras", action="store_true", help="headline workload only")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -429,6 +429,54 @@ def time_restored(step, restore, calls, warmup=2):
     return float(np.median(times))
 
 
+def bench_large_and_device_sort(args):
+    """Above 256 keys: arrays of 512..4096 keys in the fixed layout (one
+    work-group per array, runs merged in LDS), and the device-wide sort with the
+    small sorters as base case, on 2^28 uint32 keys and on 2^26 uint64 keys with
+    uint64 references (the paper's items)."""
+    import torch
+    import paper_2002_05599_amd as ss
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(21)
+    large = {}
+    for n in (512, 1024, 2048, 4096):
+        count = (1 << 26) // n
+        src = torch.randint(-2**31, 2**31 - 1, (count * n,), dtype=torch.int32, device="cuda",
+                            generator=gen).view(torch.uint32)
+        buf = src.clone()
+        ms = time_restored(lambda: ss.sort_small(buf, n), lambda: buf.copy_(src), 5)
+        large[f"u32_n{n}"] = {"count": count, "ms": ms, "keys_per_s": count * n / (ms * 1e-3),
+                              **rate(8 * count * n, ms)}
+        del src, buf
+    dev = {}
+    for name, n, kdt, vdt in (("u32_2p28", 1 << 28, torch.int32, None),
+                              ("u64_u64ref_2p26", 1 << 26, torch.int64, torch.int64)):
+        lo, hi = (-2**31, 2**31 - 1) if kdt == torch.int32 else (-2**63, 2**63 - 1)
+        src = torch.randint(lo, hi, (n,), dtype=kdt, device="cuda", generator=gen)
+        src = src.view(torch.uint32 if kdt == torch.int32 else torch.uint64)
+        vsrc = (torch.arange(n, dtype=torch.int64, device="cuda").view(torch.uint64) if vdt is not None else None)
+        kb = src.element_size() + (8 if vdt is not None else 0)
+        k = src.clone()
+        v = vsrc.clone() if vsrc is not None else None
+        ws = torch.empty(ss.sort_workspace_bytes("uint32" if kdt == torch.int32 else "uint64", n,
+                                                 8 if vdt is not None else 0), dtype=torch.uint8, device="cuda")
+
+        def restore():
+            k.copy_(src)
+            if v is not None:
+                v.copy_(vsrc)
+
+        ms = time_restored(lambda: ss.sort(k, v, workspace=ws), restore, 3, warmup=1)
+        dev[name] = {"n": n, "ms": ms, "keys_per_s": n / (ms * 1e-3), **rate(2 * kb * n, ms)}
+        del src, vsrc, k, v, ws
+    torch.cuda.empty_cache()
+    assert ss.device_status() == 0
+    return {"workload": "fixed-layout arrays of 512..4096 uint32 keys (2^26 keys per size); device-wide sort "
+                        "of 2^28 uint32 keys and of 2^26 uint64 keys + uint64 references, uniform random "
+                        "(one call includes its stream synchronisations)", "large_arrays": large,
+            "device_sort": dev}
+
+
 def seg_bytes(total, nseg, key_bytes, has_vals):
     return 2 * total * (key_bytes + (4 if has_vals else 0)) + 4 * (nseg + 1)
 
@@ -564,6 +612,7 @@ EXTRAS = [
     ("config1", bench_config1),
     ("config2", bench_config2),
     ("network_vs_insertion", bench_network_vs_insertion),
+    ("large_and_device_sort", bench_large_and_device_sort),
     ("config3_uniform", lambda a: bench_rss(a, "uniform")),
     ("config3_zipf", lambda a: bench_rss(a, "zipf")),
     ("config3_per_class", bench_rss_classes),
@@ -612,6 +661,8 @@ def main():
                "rss_zipf": bench_rss(args, "zipf", steps=args.steps, warmup=args.warmup)}
     elif w == "rss_classes":
         out = bench_rss_classes(args)
+    elif w == "large":
+        out = bench_large_and_device_sort(args)
     elif w == "is_vs_sn":
         out = bench_network_vs_insertion(args)
     elif w == "ragged":

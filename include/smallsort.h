@@ -51,6 +51,7 @@
 #ifndef SMALLSORT_H
 #define SMALLSORT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -67,6 +68,7 @@ typedef int32_t ss_status;
 #define SS_ENOMEM   (-5)  /* working memory could not be allocated */
 #define SS_ENOTUNE  (-6)  /* unknown tuning name or unreadable tuning file */
 #define SS_ESCRATCH (-7)  /* batch larger than the no-allocation entry point's scratch */
+#define SS_EWORKSPACE (-8)  /* workspace smaller than ss_sort_workspace_bytes */
 
 #define SS_MAX_NETWORK_N 16   /* largest array sorted by a network alone */
 #define SS_MAX_RSS_N    256   /* largest array sorted by Register Sample Sort alone */
@@ -151,6 +153,31 @@ ss_status ss_segmented_sort_v(int32_t key_type, void *keys, void *vals, int32_t 
 /* ss_segmented_sort_v(SS_KEY_U64, keys, refs, 8, offsets, nseg, SS_MODE_AUTO, stream). */
 ss_status segmented_sort_pairs_u64(uint64_t *keys, uint64_t *refs, const int32_t *offsets, int32_t nseg,
                                    void *stream);
+
+/*
+ * One large array sorted on the device, with the small sorters as its base
+ * case (the paper's use of them inside Quicksort and IPS4o, Sections 4.4 and
+ * 4.6, and the batching of base cases by size proposed in Section 5): sample
+ * sort partitions with about 1024 keys per bucket and equality buckets for
+ * repeated splitters, then one segmented sort of every bucket; a bucket still
+ * above 4096 keys is partitioned again.
+ *   keys:  n keys of key_type (SS_KEY_*), sorted in place (ascending; same
+ *          order as the other calls).  n: 0 .. 2^31 - 1.
+ *   vals:  NULL with val_bytes = 0, or a payload of val_bytes = 4 or 8 (8: 64-bit
+ *          keys only) per key, permuted with the keys; the order of equal keys
+ *          is unspecified.
+ *   workspace: device memory of at least ss_sort_workspace_bytes(key_type,
+ *          val_bytes, n) bytes (about n * (key + payload bytes) plus 3%),
+ *          owned by the caller; the call allocates nothing.
+ * Unlike the other calls it synchronises `stream` (between partition levels
+ * the host reads how many buckets need another level).
+ * Errors: SS_EINVAL for a bad key_type, val_bytes, n or pointer; SS_EALIGN for
+ * misaligned keys or vals; SS_EWORKSPACE if the workspace is too small;
+ * SS_EHIP if a launch fails.
+ */
+size_t ss_sort_workspace_bytes(int32_t key_type, int32_t val_bytes, int64_t n);
+ss_status ss_sort(int32_t key_type, void *keys, void *vals, int32_t val_bytes, int64_t n, void *workspace,
+                  size_t workspace_bytes, void *stream);
 
 /*
  * No-allocation form of ss_segmented_sort, for callers that cannot allocate

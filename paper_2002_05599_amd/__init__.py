@@ -18,7 +18,7 @@ __all__ = [
     "SmallSortError", "lib", "lib_path", "sort_small", "segmented_sort", "device_status",
     "set_tuning", "get_tuning", "load_tuning", "tuning_path", "version", "KEY_CODES",
     "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN", "stream_copy", "segmented_sort_noalloc",
-    "NOALLOC_MAX_SEGMENTS",
+    "NOALLOC_MAX_SEGMENTS", "sort", "sort_workspace_bytes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -47,6 +47,8 @@ _SIGS = {
     "ss_segmented_sort_v": (ctypes.c_int32, [ctypes.c_int32, _P, _P, ctypes.c_int32, _P, ctypes.c_int32,
                                              ctypes.c_int32, _P]),
     "segmented_sort_pairs_u64": (ctypes.c_int32, [_P, _P, _P, ctypes.c_int32, _P]),
+    "ss_sort_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]),
+    "ss_sort": (ctypes.c_int32, [ctypes.c_int32, _P, _P, ctypes.c_int32, ctypes.c_int64, _P, ctypes.c_size_t, _P]),
 }
 
 NOALLOC_MAX_SEGMENTS = 1 << 24  # SS_NOALLOC_MAX_SEGMENTS
@@ -224,6 +226,35 @@ def segmented_sort_noalloc(keys, offsets, vals=None, stream=None):
     st = lib().ss_segmented_sort_noalloc(KEY_CODES[name], ctypes.c_void_p(keys.data_ptr()), vptr,
                                          ctypes.c_void_p(offsets.data_ptr()), max(nseg, 0), _stream_ptr(stream))
     _check(st, "ss_segmented_sort_noalloc")
+    return keys, vals
+
+
+def sort_workspace_bytes(dtype_name, n, val_bytes=0) -> int:
+    """Device workspace ``sort`` needs for n keys of the named dtype."""
+    return int(lib().ss_sort_workspace_bytes(KEY_CODES[dtype_name], int(val_bytes), int(n)))
+
+
+def sort(keys, vals=None, workspace=None, stream=None):
+    """Sort the whole 1-D device tensor ``keys`` (and ``vals``, uint32 or
+    uint64) in place: the device-wide sort with the small sorters as base
+    case.  ``workspace``: a device tensor of at least sort_workspace_bytes
+    bytes; if omitted, one is allocated with torch for this call."""
+    import torch
+    _require_cuda(keys, "keys")
+    name = _dtype_name(keys)
+    vptr, vbytes = None, 0
+    if vals is not None:
+        _require_cuda(vals, "vals")
+        if str(vals.dtype) not in ("torch.uint32", "torch.uint64") or vals.numel() != keys.numel():
+            raise TypeError("vals must be a uint32 or uint64 tensor shaped like keys")
+        vptr, vbytes = ctypes.c_void_p(vals.data_ptr()), vals.element_size()
+    need = sort_workspace_bytes(name, keys.numel(), vbytes)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+    st = lib().ss_sort(KEY_CODES[name], ctypes.c_void_p(keys.data_ptr()), vptr, vbytes, keys.numel(),
+                       ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                       _stream_ptr(stream))
+    _check(st, "ss_sort")
     return keys, vals
 
 

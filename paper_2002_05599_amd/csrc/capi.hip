@@ -276,6 +276,35 @@ ss_status segmented_sort_pairs_u64(uint64_t* keys, uint64_t* refs, const int32_t
   return segmented(SS_KEY_U64, keys, refs, 8, offsets, nseg, SS_MODE_AUTO, static_cast<hipStream_t>(stream));
 }
 
+size_t ss_sort_workspace_bytes(int32_t key_type, int32_t val_bytes, int64_t n) {
+  if (key_type < SS_KEY_U32 || key_type > SS_KEY_F64 || n < 0 || n > INT32_MAX) return 0;
+  if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return 0;
+  if (val_bytes == 8 && !key_is_64(key_type)) return 0;
+  return devsort_workspace_bytes(n, key_is_64(key_type) ? 8 : 4, val_bytes);
+}
+
+ss_status ss_sort(int32_t key_type, void* keys, void* vals, int32_t val_bytes, int64_t n, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  if (key_type < SS_KEY_U32 || key_type > SS_KEY_F64) return SS_EINVAL;
+  if (val_bytes != 0 && val_bytes != 4 && val_bytes != 8) return SS_EINVAL;
+  if (val_bytes == 8 && !key_is_64(key_type)) return SS_EINVAL;
+  if ((vals == nullptr) != (val_bytes == 0)) return SS_EINVAL;
+  if (n < 0 || n > INT32_MAX) return SS_EINVAL;
+  if (n <= 1) return SS_OK;
+  if (keys == nullptr || workspace == nullptr) return SS_EINVAL;
+  const size_t ksz = key_is_64(key_type) ? 8 : 4;
+  if (reinterpret_cast<uintptr_t>(keys) % ksz != 0) return SS_EALIGN;
+  if (vals && reinterpret_cast<uintptr_t>(vals) % (size_t)val_bytes != 0) return SS_EALIGN;
+  if (workspace_bytes < devsort_workspace_bytes(n, (int)ksz, val_bytes)) return SS_EWORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = key_is_64(key_type)
+                     ? devsort_u64(static_cast<uint64_t*>(keys), vals, val_bytes, n, workspace, workspace_bytes,
+                                   key_map<uint64_t>(key_type), s)
+                     : devsort_u32(static_cast<uint32_t*>(keys), vals, val_bytes, n, workspace, workspace_bytes,
+                                   key_map<uint32_t>(key_type), s);
+  return from_hip(e);
+}
+
 ss_status ss_segmented_sort_noalloc(int32_t key_type, void* keys, uint32_t* vals, const int32_t* offsets,
                                     int32_t nseg, void* stream) {
   return segmented_noalloc(key_type, keys, vals, offsets, nseg, static_cast<hipStream_t>(stream));
@@ -307,6 +336,7 @@ const char* ss_strerror(ss_status status) {
     case SS_ENOMEM: return "out of device memory";
     case SS_ENOTUNE: return "unknown tuning parameter or unreadable tuning file";
     case SS_ESCRATCH: return "batch exceeds the fixed working memory of the no-allocation entry point";
+    case SS_EWORKSPACE: return "workspace smaller than ss_sort_workspace_bytes";
     default: return "unknown status";
   }
 }

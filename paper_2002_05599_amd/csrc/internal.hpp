@@ -40,6 +40,14 @@ hipError_t launch_large_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t 
 hipError_t launch_large_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                                   hipStream_t s);
 
+// One large array (n < 2^31) sorted with the small sorters as base case
+// (devsort.hip); vb = payload bytes (0, 4, 8); synchronises s.
+size_t devsort_workspace_bytes(int64_t n, int key_bytes, int val_bytes);
+hipError_t devsort_u32(uint32_t* keys, void* vals, int vb, int64_t n, void* ws, size_t ws_bytes,
+                       KeyMap<uint32_t> map, hipStream_t s);
+hipError_t devsort_u64(uint64_t* keys, void* vals, int vb, int64_t n, void* ws, size_t ws_bytes,
+                       KeyMap<uint64_t> map, hipStream_t s);
+
 // Streaming device-to-device copy of `bytes` (the read-once / write-once
 // ceiling the sorting kernels are measured against).
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
@@ -62,6 +70,7 @@ struct SegBuffers {
   int32_t* ids = nullptr;
   uint32_t* ctrl = nullptr;
   uint32_t* blockhist = nullptr;
+  bool quiet = false;  // skip segments above 4096 keys without flagging them in the status word
 };
 
 // Largest batch of the no-allocation segmented entry point (its segment-id

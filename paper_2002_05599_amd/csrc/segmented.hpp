@@ -761,7 +761,7 @@ struct SegLaunch {
     offsets = off;
     nseg = n;
     blockhist = s.blockhist;
-    status = c->status;
+    status = s.quiet ? nullptr : c->status;
     nblocks = kBinBlocks;
     ctrl = s.ctrl;
     ctrl_c = s.ctrl;

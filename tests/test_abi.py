@@ -134,3 +134,18 @@ def test_library_leaves_no_symbol_of_its_own_undefined():
     r = subprocess.run(["nm", "-uC", ss.lib_path()], capture_output=True, text=True, check=True)
     missing = [ln for ln in r.stdout.splitlines() if "ss::" in ln]
     assert not missing, missing
+
+
+def test_device_sort_workspace_size(lib):
+    """ss_sort_workspace_bytes: 0 for invalid arguments, about the data size
+    plus a few percent for large n, growing with n."""
+    f = lib.ss_sort_workspace_bytes
+    assert f(9, 0, 100) == 0 and f(0, 8, 100) == 0 and f(0, 3, 100) == 0 and f(0, 0, -1) == 0
+    assert f(0, 0, 2**31) == 0
+    for kt, kb in ((0, 4), (2, 8)):
+        for vb in (0, 4):
+            n = 10_000_000
+            w = f(kt, vb, n)
+            assert n * (kb + vb) <= w <= 1.2 * n * (kb + vb) + (1 << 20)
+            assert f(kt, vb, n // 10) < w
+    assert f(2, 8, 1000) > 0
