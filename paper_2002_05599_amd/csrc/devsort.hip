@@ -10,7 +10,9 @@
 //   classify  a key e goes to bucket 2j, j = #{splitters < e}, or to the
 //             equality bucket 2j + 1 when e == s_j (IPS4o's equality
 //             buckets: a value that fills several splitters lands in one
-//             bucket that needs no sorting), branch-free binary search;
+//             bucket that needs no sorting); branch-free binary searches,
+//             first over every 256th splitter held in LDS, then inside
+//             the block of 256 splitters it selects;
 //   count     one atomic counter per bucket; an exclusive scan gives the
 //             bucket offsets;
 //   scatter   every key (and payload) to its bucket in the temporary buffer.
@@ -59,21 +61,49 @@ ds_splitter_kernel(const K* __restrict__ sorted_sample, K* __restrict__ spl, int
     spl[i] = map.enc(sorted_sample[(int64_t)i * kDsOversample + kDsOversample / 2]);
 }
 
-// bucket of word e: 2j or 2j + 1 (see above); `top` = largest power of two <= nspl
+// The splitter search in two steps: the last splitter of every block of
+// kDsBlock splitters is held in LDS (at most kDsTop of them), a binary search
+// there gives the block, a second one inside the block (a few cache lines of
+// global memory) gives j.
+constexpr int kDsBlock = 256;
+constexpr int kDsTop = (kDsMaxSplitters + kDsBlock) / kDsBlock;  // 4096
+
 template <class K>
-__device__ __forceinline__ int ds_bucket(K e, const K* __restrict__ spl, int nspl, int top) {
-  int j = 0;
-  for (int step = top; step >= 1; step >>= 1)
-    if (j + step <= nspl && spl[j + step - 1] < e) j += step;
+__device__ __forceinline__ int ds_load_top(K* top, const K* __restrict__ spl, int nspl) {
+  const int nt = (nspl + kDsBlock - 1) / kDsBlock;
+  for (int t = threadIdx.x; t < nt; t += kDsThreads) top[t] = spl[min((t + 1) * kDsBlock, nspl) - 1];
+  __syncthreads();
+  return nt;
+}
+
+// largest power of two <= x (x >= 1)
+__device__ __forceinline__ int ds_pow2_floor(int x) { return 1 << (31 - __builtin_clz((unsigned)x)); }
+
+// bucket of word e: 2j or 2j + 1 with j = #{splitters < e} (see above)
+template <class K>
+__device__ __forceinline__ int ds_bucket(K e, const K* top, int nt, const K* __restrict__ spl, int nspl) {
+  int tb = 0;  // blocks whose last splitter is below e: all their splitters are
+  for (int step = ds_pow2_floor(nt); step >= 1; step >>= 1)
+    if (tb + step <= nt && top[tb + step - 1] < e) tb += step;
+  int j = min(tb * kDsBlock, nspl);  // every splitter is below e when tb == nt
+  if (tb < nt) {
+    const int len = min(kDsBlock, nspl - j);
+    int r = 0;
+    for (int step = kDsBlock / 2; step >= 1; step >>= 1)
+      if (r + step <= len && spl[j + r + step - 1] < e) r += step;
+    j += r;
+  }
   return 2 * j + ((j < nspl && spl[j] == e) ? 1 : 0);
 }
 
 template <class K>
 __global__ void __launch_bounds__(kDsThreads)
-ds_count_kernel(const K* __restrict__ keys, int64_t n, const K* __restrict__ spl, int nspl, int top,
+ds_count_kernel(const K* __restrict__ keys, int64_t n, const K* __restrict__ spl, int nspl,
                 uint32_t* __restrict__ counts, KeyMap<K> map) {
+  __shared__ K top[kDsTop];
+  const int nt = ds_load_top(top, spl, nspl);
   for (int64_t i = (int64_t)blockIdx.x * kDsThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kDsThreads)
-    atomicAdd(&counts[ds_bucket(map.enc(keys[i]), spl, nspl, top)], 1u);
+    atomicAdd(&counts[ds_bucket(map.enc(keys[i]), top, nt, spl, nspl)], 1u);
 }
 
 // One work-group: exclusive scan of the bucket counts into offsets[0..nb]
@@ -110,11 +140,13 @@ ds_scan_kernel(const uint32_t* __restrict__ counts, int nb, int32_t* __restrict_
 template <class K, int V>
 __global__ void __launch_bounds__(kDsThreads)
 ds_scatter_kernel(const K* __restrict__ keys, const Pay<V>* __restrict__ vals, int64_t n,
-                  const K* __restrict__ spl, int nspl, int top, uint32_t* __restrict__ cursors,
+                  const K* __restrict__ spl, int nspl, uint32_t* __restrict__ cursors,
                   K* __restrict__ out_keys, Pay<V>* __restrict__ out_vals, KeyMap<K> map) {
+  __shared__ K top[kDsTop];
+  const int nt = ds_load_top(top, spl, nspl);
   for (int64_t i = (int64_t)blockIdx.x * kDsThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kDsThreads) {
     const K x = keys[i];
-    const uint32_t pos = atomicAdd(&cursors[ds_bucket(map.enc(x), spl, nspl, top)], 1u);
+    const uint32_t pos = atomicAdd(&cursors[ds_bucket(map.enc(x), top, nt, spl, nspl)], 1u);
     out_keys[pos] = x;
     if constexpr (V) out_vals[pos] = vals[i];
   }
@@ -263,16 +295,14 @@ static hipError_t ds_sort(DeviceCtx* c, K* keys, Pay<V>* vals, int64_t n, K* tmp
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ds_splitter_kernel<K>, dim3(ds_grid(c, p.nspl)), dim3(kDsThreads), 0, s, sample, spl, p.nspl,
                      map);
-  int top = 1;
-  while (top * 2 <= p.nspl) top *= 2;
 
   // count, scan, scatter into the temporary buffer
   e = hipMemsetAsync(counts, 0, (size_t)(p.nb + 1) * 4, s);
   if (e == hipSuccess) e = hipMemsetAsync(nbig, 0, 4, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ds_count_kernel<K>, dim3(g), dim3(kDsThreads), 0, s, keys, n, spl, p.nspl, top, counts, map);
+  hipLaunchKernelGGL(ds_count_kernel<K>, dim3(g), dim3(kDsThreads), 0, s, keys, n, spl, p.nspl, counts, map);
   hipLaunchKernelGGL(ds_scan_kernel, dim3(1), dim3(1024), 0, s, counts, p.nb, offsets, cursors, big, nbig);
-  hipLaunchKernelGGL((ds_scatter_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, n, spl, p.nspl, top,
+  hipLaunchKernelGGL((ds_scatter_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, n, spl, p.nspl,
                      cursors, tmp_keys, tmp_vals, map);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
