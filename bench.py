@@ -164,7 +164,7 @@ def bench_fixed16(args):
     algo_bytes = 2 * nkeys * 4
     achieved = algo_bytes / (ms * 1e-3) / 1e9
     kkey = "fixed_tile_kernel<n=16,u32>"
-    family = ss.get_tuning("family")
+    family = ss.get_tuning("u32.family")
     del bufs, keys
     torch.cuda.empty_cache()
     return {
@@ -357,7 +357,7 @@ def bench_network_vs_insertion(args):
     count = 1 << 24
     gen = torch.Generator(device="cuda")
     gen.manual_seed(12)
-    fam0 = ss.get_tuning("family")
+    fam0 = {w: ss.get_tuning(f"{w}.family") for w in ("u32", "u64")}
     rows = {}
     try:
         for dtype, kb in (("u32", 4), ("i64", 8)):
@@ -379,7 +379,8 @@ def bench_network_vs_insertion(args):
                     del src, buf
                 rows[f"{dtype}_n{n}"] = row
     finally:
-        ss.set_tuning("family", fam0)
+        for w, f in fam0.items():
+            ss.set_tuning(f"{w}.family", f)
     torch.cuda.empty_cache()
     # 17..256 keys: RSS (network base case), RSS with insertion-sort base case, IS+SN
     keys, off = inputs.config3(nseg=1 << 20, dist="uniform")

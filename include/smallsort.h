@@ -210,12 +210,24 @@ ss_status ss_device_status(void *stream, int32_t *out);
 const char *ss_strerror(ss_status status);
 
 /*
- * Tuning parameters (variant choices found by the autotuner).  Names:
- *   "family"       network family: 0 = fewest comparators, 1 = Bose-Nelson
+ * Tuning parameters (variant choices found by the autotuner).  The first
+ * eight are kept per key width: "<name>" sets both widths, "u32.<name>" or
+ * "u64.<name>" one of them (32-bit keys: uint32, int32, float; 64-bit keys:
+ * uint64, int64, double); getting "<name>" returns -2 when the widths differ.
+ *   "family"       n <= 16: 0 = fewest-comparator networks, 1 = Bose-Nelson
+ *                  networks, 2 = insertion sort (the paper's baseline)
  *   "rss_k_small"  buckets (4, 8 or 16; splitters + 1) of the first Register
- *                  Sample Sort level for arrays of 17..64 keys
- *   "rss_k_mid"    same for arrays of 65..128 keys (4, 8, 16 or 32)
- *   "rss_k_large"  same for arrays of 129..256 keys (4, 8, 16, 32 or 64)
+ *                  Sample Sort level for arrays of the 16-lane class
+ *   "rss_k_mid"    same for the 32-lane class (4, 8, 16 or 32)
+ *   "rss_k_large"  same for the 64-lane class (4, 8, 16, 32 or 64)
+ *   "rss_bound_small" arrays of 17..bound_small keys are sorted by 16 lanes
+ *                  (16..64, default 64; at most 4 keys per lane)
+ *   "rss_bound_mid" arrays of bound_small+1..bound_mid keys by 32 lanes
+ *                  (bound_small..128, default 128), larger ones by 64 lanes
+ *   "rss_oversample" oversampling factor a of the Register Sample Sort levels
+ *                  with 4 buckets (1..4, default 3: the paper's "332")
+ *   "fixed_apt"    arrays per thread of the fixed-layout network kernels (1, 2
+ *                  or 4; reduced where the tile would not fit 32 KiB of LDS)
  *   "persist_occ"  work-groups per CU of the persistent grid (0 = as many as
  *                  fit, 1..16)
  *   "rss_rounds"   most rounds of lane groups per RSS tile in segmented sorts
@@ -235,8 +247,12 @@ const char *ss_strerror(ss_status status);
  *                  rank-counting sort (each key placed at the number of keys
  *                  that precede it); lower values exist to test and measure
  *                  that fallback.
- * ss_set_tuning_value returns SS_ENOTUNE for an unknown name, SS_EINVAL for a
- * value out of range.  ss_get_tuning_value returns -1 for an unknown name.
+ *   "large_sort"   1: arrays of more than 16 keys are sorted by insertion sort
+ *                  (the paper's IS+SN hybrid, Section 4.6); 0: Register Sample
+ *                  Sort (default)
+ * ss_set_tuning_value returns SS_ENOTUNE for an unknown name (or a width
+ * prefix on a knob that has one value), SS_EINVAL for a value out of range.
+ * ss_get_tuning_value returns -1 for an unknown name.
  * ss_load_tuning reads a flat JSON object {"name": integer, ...} with these
  * names (other keys are ignored); SS_ENOTUNE if the file cannot be read or
  * parsed.  Settings are process-wide and apply to later calls.

@@ -1,29 +1,37 @@
 """Autotuner for the library's variant choices (run on the GPU).
 
-Knobs (see include/smallsort.h): network family; first-level bucket count of
-Register Sample Sort per size class; the most rounds of lane groups per RSS
-tile, one persistent kernel per kind or one for all, tile interleaving (single
-kernel) and work-groups per CU of the persistent ragged kernels.  The paper
-found the best variant and RSS parameters to differ from machine to machine
-(Sections 4.2 and 4.5); here they are measured on the GPU at hand.
+The paper found the best network variant and the best Register Sample Sort
+parameters to differ from machine to machine (Sections 4.2 and 4.5); here
+they are measured on the GPU at hand, separately for 32-bit and 64-bit keys.
 
-Workloads: fixed-size arrays of 4..16 keys (family); one CSR batch per RSS
-size class (its bucket count); for the segmented-sort knobs the sum of the
-10^7-segment ragged batch with payload and the 2^20-array RSS-only batch, at
-the sizes the benchmark uses (a quarter of each with --quick).
+Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
+  family           network family or insertion sort (fixed arrays of 4..16 keys
+                   plus the RSS batches, whose buckets the networks finish)
+  fixed_apt        arrays per thread of the fixed-layout kernels (items per
+                   thread; fixed arrays of 2..8 keys)
+  rss_bound_small, rss_bound_mid
+                   the wave-to-segment mapping: which segment sizes get 16, 32
+                   or 64 lanes (a CSR batch of 17..128 keys)
+  rss_k_small/mid/large
+                   first-level bucket count of each lane-group class (a CSR
+                   batch of sizes within the class)
+  rss_oversample   oversampling a of the 4-bucket levels (the RSS batch)
+For every width together (the ragged 10^7-segment batch plus the 2^20-array
+RSS batch): rss_rounds, persist_split, net_mix, interleave, persist_occ.
 
-Method: coordinate descent.  For each knob in turn every allowed value is
-timed on a representative workload with the other knobs fixed, and the
-fastest is kept if it beats the current value by more than 1% (otherwise the
-current value stays).  A measurement is the median over ``reps`` calls, each on a
-fresh copy of the input (restored outside the timed region) and bracketed by
-HIP events on the calling stream.
+Method: coordinate descent.  For each knob every allowed value is timed with
+the others fixed (median of ``reps`` calls, each on a fresh copy of the input
+restored outside the timed region, bracketed by HIP events on the calling
+stream); the fastest replaces the current value only if it is faster by more
+than 1%.  Every candidate's output is compared, bit for bit, with the output
+of the library's default settings on the same input (sorting has one correct
+result: keys always, payloads where keys are distinct); a candidate that
+differs is rejected and reported.
 
-The result is a flat JSON object ({"knob": value, ..., "arch": ..., "rocm":
-...}) that ``ss_load_tuning`` reads; the binding loads
+The result is a flat JSON object ({"u32.family": 1, ..., "rss_rounds": 64,
+"arch": ..., "rocm": ...}) that ``ss_load_tuning`` reads; the binding loads
 ``tuning_<arch>.json`` next to the library automatically when its arch and
-ROCm version match the running system.  A separate report records every
-measurement.
+ROCm version match.  The report records every measurement in ms and GB/s.
 
     python -m paper_2002_05599_amd.autotune [--quick] [--out PATH] [--report PATH]
 """
@@ -37,6 +45,11 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
+PER_WIDTH = ("family", "fixed_apt", "rss_bound_small", "rss_bound_mid", "rss_k_small", "rss_k_mid",
+             "rss_k_large", "rss_oversample")
+GLOBAL = ("rss_rounds", "persist_split", "net_mix", "interleave", "persist_occ")
+NOISE = 0.01
+
 
 def system_tag():
     import torch
@@ -49,132 +62,158 @@ def default_path(arch=None):
     return os.path.join(HERE, f"tuning_{arch or 'gfx950'}.json")
 
 
-def _timer(fn, restore, reps):
-    import torch
-    stream = torch.cuda.current_stream()
-    times = []
-    for _ in range(reps):
-        restore()
+class Case:
+    """One timed input: device buffers, pristine copies, the call that sorts
+    them, the bytes it must move, and the reference output."""
+
+    def __init__(self, name, call, bufs, nbytes):
+        self.name = name
+        self.call = call            # call(bufs) sorts bufs in place
+        self.bufs = bufs            # device tensors sorted in place
+        self.src = [b.clone() for b in bufs]
+        self.nbytes = nbytes
+        self.ref = None
+
+    def restore(self):
+        for b, s in zip(self.bufs, self.src):
+            b.copy_(s)
+
+    def time(self, reps):
+        """Median event time of one call (ms); the last call's output stays in bufs."""
+        import torch
+        stream = torch.cuda.current_stream()
+        times = []
+        for _ in range(reps):
+            self.restore()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            self.call(self.bufs)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return float(np.median(times))
+
+    def record_reference(self):
+        import torch
+        self.restore()
+        self.call(self.bufs)
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fn()
-        e1.record(stream)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-    return float(np.median(times))
+        self.ref = [b.clone() for b in self.bufs]
+
+    def output_matches(self):
+        import torch
+        torch.cuda.synchronize()
+        return all(torch.equal(b.view(torch.uint8), r.view(torch.uint8)) for b, r in zip(self.bufs, self.ref))
+
+
+def _fixed_case(width, n, count, seed):
+    import torch
+    from . import inputs, sort_small
+    dt = np.uint32 if width == "u32" else np.uint64
+    a = torch.from_numpy(inputs.fixed_keys(dt, n, count, "uniform", seed=seed)).cuda()
+    return Case(f"{width} fixed n={n}", lambda b: sort_small(b[0], n), [a], 2 * a.numel() * a.element_size())
+
+
+def _csr_case(width, nseg, lo, hi, seed):
+    import torch
+    from . import inputs, segmented_sort
+    off = inputs.offsets_from_sizes(inputs.csr_sizes(nseg, lo, hi, seed=seed))
+    total = int(off[-1])
+    to = torch.from_numpy(off).cuda()
+    if width == "u32":
+        k = torch.from_numpy(inputs.random_keys(np.uint32, total, seed=lo)).cuda()
+        return Case(f"u32 CSR {lo}..{hi}", lambda b: segmented_sort(b[0], to), [k], 8 * total + 4 * nseg)
+    k = torch.from_numpy(inputs.distinct_u64(total, seed=lo)).cuda()
+    v = torch.from_numpy(inputs.segment_index_payload(off)).cuda()
+    return Case(f"u64+payload CSR {lo}..{hi}", lambda b: segmented_sort(b[0], to, b[1]), [k, v],
+                24 * total + 4 * nseg)
 
 
 class Workloads:
-    """Representative inputs, resident on the device, with pristine copies."""
+    """Representative inputs per key width, resident on the device."""
 
     def __init__(self, quick=False):
         import torch
-        from . import inputs
-        scale = 4 if quick else 1
-        # fixed-size arrays for the network family (u32 and u64)
-        self.fixed = []
-        for dt in (np.uint32, np.uint64):
-            for n in (4, 8, 12, 16):
-                a = torch.from_numpy(inputs.fixed_keys(dt, n, (1 << 22) // scale, "uniform", seed=n)).cuda()
-                self.fixed.append((n, a, a.clone()))
-        # RSS classes: CSR batches with sizes inside each class
-        self.rss = {}
-        for knob, lo, hi in (("rss_k_small", 17, 64), ("rss_k_mid", 65, 128), ("rss_k_large", 129, 256)):
-            off = inputs.offsets_from_sizes(inputs.csr_sizes((1 << 18) // scale, lo, hi, seed=hi))
-            k = torch.from_numpy(inputs.random_keys(np.uint64, int(off[-1]), seed=lo)).cuda()
-            self.rss[knob] = (k, k.clone(), torch.from_numpy(off).cuda())
-        # ragged batch of the 10^7-segment benchmark (a quarter with --quick)
-        k, v, off = inputs.config4(nseg=10_000_000 // scale, seed=44)
-        self.ragged = (torch.from_numpy(k).cuda(), torch.from_numpy(v).cuda(), torch.from_numpy(off).cuda())
-        self.ragged_src = tuple(t.clone() for t in self.ragged[:2])
-        # RSS-only batch of the 2^20-array benchmark: int32 arrays of 17..256 keys
-        k, off = inputs.config3(nseg=(1 << 20) // scale, dist="uniform", seed=7)
-        k = torch.from_numpy(k).cuda()
-        self.rss_all = (k, k.clone(), torch.from_numpy(off).cuda())
+        from . import inputs, segmented_sort
+        d = 4 if quick else 1
+        self.cases = {}
+        for w in ("u32", "u64"):
+            self.cases[(w, "family")] = ([_fixed_case(w, n, (1 << 22) // d, n) for n in (4, 8, 12, 16)]
+                                         + [_csr_case(w, (1 << 18) // d, 17, 256, 5)])
+            self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8)]
+            self.cases[(w, "rss_bound_small")] = [_csr_case(w, (1 << 19) // d, 17, 128, 7)]
+            self.cases[(w, "rss_bound_mid")] = self.cases[(w, "rss_bound_small")]
+            self.cases[(w, "rss_k_small")] = [_csr_case(w, (1 << 18) // d, 17, 64, 64)]
+            self.cases[(w, "rss_k_mid")] = [_csr_case(w, (1 << 18) // d, 65, 128, 128)]
+            self.cases[(w, "rss_k_large")] = [_csr_case(w, (1 << 18) // d, 129, 256, 256)]
+            self.cases[(w, "rss_oversample")] = [_csr_case(w, (1 << 19) // d, 17, 256, 9)]
+        # global knobs: the ragged batch (u64 + payload) and the RSS-only batch (int32)
+        k, v, off = inputs.config4(nseg=10_000_000 // d, seed=44)
+        to = torch.from_numpy(off).cuda()
+        ragged = Case("ragged 10^7 u64+payload", lambda b: segmented_sort(b[0], to, b[1]),
+                      [torch.from_numpy(k).cuda(), torch.from_numpy(v).cuda()],
+                      24 * int(off[-1]) + 4 * (off.size - 1))
+        k3, off3 = inputs.config3(nseg=(1 << 20) // d, dist="uniform", seed=7)
+        to3 = torch.from_numpy(off3).cuda()
+        rss = Case("RSS 2^20 int32", lambda b: segmented_sort(b[0], to3), [torch.from_numpy(k3).cuda()],
+                   8 * int(off3[-1]) + 4 * (off3.size - 1))
+        for g in GLOBAL:
+            self.cases[("all", g)] = [ragged, rss]
         torch.cuda.synchronize()
 
-    def time_family(self, reps):
-        """The family shapes the fixed-size sorts and every network inside RSS."""
-        from . import sort_small
-        total = 0.0
-        for n, a, src in self.fixed:
-            total += _timer(lambda: sort_small(a, n), lambda: a.copy_(src), reps)
-        for knob in self.rss:
-            total += self.time_rss(knob, reps)
-        return total
-
-    def time_rss(self, knob, reps):
-        from . import segmented_sort
-        k, src, off = self.rss[knob]
-        return _timer(lambda: segmented_sort(k, off), lambda: k.copy_(src), reps)
-
-    def time_ragged_only(self, reps, mode=0):
-        from . import segmented_sort
-        k, v, off = self.ragged
-
-        def restore():
-            k.copy_(self.ragged_src[0])
-            v.copy_(self.ragged_src[1])
-
-        return _timer(lambda: segmented_sort(k, off, v, mode=mode), restore, reps)
-
-    def time_rss_all(self, reps, mode=0):
-        from . import segmented_sort
-        k, src, off = self.rss_all
-        return _timer(lambda: segmented_sort(k, off, mode=mode), lambda: k.copy_(src), reps)
-
-    def time_ragged(self, reps, mode=0):
-        """Objective of the segmented-sort knobs: ragged batch + RSS-only batch."""
-        return self.time_ragged_only(reps, mode) + self.time_rss_all(reps, mode)
+    def all_cases(self):
+        seen = {}
+        for cs in self.cases.values():
+            for c in cs:
+                seen[id(c)] = c
+        return list(seen.values())
 
 
-NOISE = 0.01
-
-SPACE = [
-    ("family", [0, 1], "family"),
-    ("rss_k_small", [4, 8, 16], "rss"),
-    ("rss_k_mid", [4, 8, 16, 32], "rss"),
-    ("rss_k_large", [4, 8, 16, 32, 64], "rss"),
-    ("rss_rounds", [4, 8, 16, 32, 64], "ragged"),
-    ("persist_split", [0, 1], "ragged"),
-    ("net_mix", [0, 1], "ragged"),
-    ("interleave", [0, 1], "ragged"),
-    ("persist_occ", [0, 1, 2, 3], "ragged"),
-]
+def candidates(name):
+    return {"family": [0, 1, 2], "fixed_apt": [1, 2, 4], "rss_bound_small": [16, 32, 48, 64],
+            "rss_bound_mid": [64, 96, 128], "rss_k_small": [4, 8, 16], "rss_k_mid": [4, 8, 16, 32],
+            "rss_k_large": [4, 8, 16, 32, 64], "rss_oversample": [1, 2, 3, 4], "rss_rounds": [4, 8, 16, 32, 64],
+            "persist_split": [0, 1], "net_mix": [0, 1], "interleave": [0, 1], "persist_occ": [0, 1, 2, 3]}[name]
 
 
 def tune(quick=False, reps=5, log=print):
-    from . import get_tuning, set_tuning
+    from . import SmallSortError, get_tuning, set_tuning
     w = Workloads(quick=quick)
-    best = {name: get_tuning(name) for name, _, _ in SPACE}
-    report = {}
-    for name, values, kind in SPACE:
-        results = {}
-        for v in values:
-            set_tuning(name, v)
-            if kind == "family":
-                ms = w.time_family(reps)
-            elif kind == "rss":
-                ms = w.time_rss(name, reps)
-            else:
-                ms = w.time_ragged(reps)
-            results[v] = ms
-            log(f"  {name}={v}: {ms:.4f} ms")
-        # keep the current value unless another is faster by more than the noise
-        # threshold (1%)
-        choice = min(results, key=results.get)
-        if best[name] in results and results[choice] > (1.0 - NOISE) * results[best[name]]:
-            choice = best[name]
+    # reference outputs under the library's defaults (the tested configuration)
+    for c in w.all_cases():
+        c.record_reference()
+    best, report = {}, {}
+    order = [(wd, k) for wd in ("u32", "u64") for k in PER_WIDTH] + [("all", k) for k in GLOBAL]
+    for width, knob in order:
+        name = knob if width == "all" else f"{width}.{knob}"
+        current = get_tuning(name)
+        cases = w.cases[(width, knob)]
+        results, rejected = {}, []
+        for v in candidates(knob):
+            try:
+                set_tuning(name, v)
+            except SmallSortError:
+                continue  # not valid with the other current values (a bound pair)
+            ms, ok = 0.0, True
+            for c in cases:
+                ms += c.time(reps)
+                ok = ok and c.output_matches()
+            if not ok:
+                rejected.append(v)
+                log(f"  {name}={v}: output differs from the reference -- rejected")
+                continue
+            nbytes = sum(c.nbytes for c in cases)
+            results[v] = {"ms": ms, "GBps": nbytes / (ms * 1e-3) / 1e9}
+            log(f"  {name}={v}: {ms:.4f} ms  {results[v]['GBps']:.1f} GB/s")
+        choice = min(results, key=lambda v: results[v]["ms"]) if results else current
+        if current in results and results[choice]["ms"] > (1.0 - NOISE) * results[current]["ms"]:
+            choice = current
         set_tuning(name, choice)
         best[name] = choice
-        report[name] = {"ms": {str(k): v for k, v in results.items()}, "best": choice}
+        report[name] = {"workloads": [c.name for c in cases], "results": {str(k): r for k, r in results.items()},
+                        "rejected": rejected, "best": choice}
         log(f"{name} -> {choice}")
-    # tuned persistent graph form vs one launch per size class
-    for mode, name in ((0, "graph"), (2, "plain")):
-        report[f"ragged_{name}_ms"] = w.time_ragged_only(reps, mode)
-        report[f"rss_{name}_ms"] = w.time_rss_all(reps, mode)
     return best, report
 
 
@@ -190,7 +229,6 @@ def main():
     arch, rocm = system_tag()
     t0 = time.time()
     best, report = tune(quick=args.quick, reps=args.reps, log=lambda s: print(s, flush=True))
-    print(json.dumps({k: v for k, v in report.items() if k.endswith("_ms")}), flush=True)
     out = args.out or default_path(arch)
     doc = dict(best)
     doc.update({"arch": arch, "rocm": rocm})

@@ -15,13 +15,14 @@
 
 namespace ss {
 
-// The process-wide tuning values; read and written only under g_tune_mu.
+// The process-wide tuning values, one set per key width (index 0: 32-bit
+// keys, 1: 64-bit keys); read and written only under g_tune_mu.
 static std::mutex g_tune_mu;
-static Tuning g_tuning;
+static Tuning g_tuning[2];
 
-Tuning tuning() {
+Tuning tuning(int key_bytes) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  return g_tuning;
+  return g_tuning[key_bytes == 8 ? 1 : 0];
 }
 
 static std::mutex g_ctx_mu;
@@ -176,40 +177,76 @@ static ss_status segmented_noalloc(int32_t key_type, void* keys, uint32_t* vals,
 
 struct TuneEntry {
   const char* name;
-  int* slot;
+  int Tuning::*slot;
   int lo, hi;
-  bool pow2_k;  // a bucket count: a power of two in [lo, hi]
+  bool pow2_k;     // a bucket count: a power of two in [lo, hi]
+  bool per_width;  // kept per key width ("u32.<name>" / "u64.<name>"); else one value
 };
 
-// Entries point into g_tuning: use under g_tune_mu.
-static std::vector<TuneEntry> tune_table() {
-  Tuning& t = g_tuning;
-  return {
-      {"family", &t.family, 0, 2, false},
-      {"rss_k_small", &t.rss_k[0], 4, 16, true},
-      {"rss_k_mid", &t.rss_k[1], 4, 32, true},
-      {"rss_k_large", &t.rss_k[2], 4, 64, true},
-      {"persist_occ", &t.persist_occ, 0, 16, false},
-      {"rss_rounds", &t.rss_rounds, 1, 64, false},
-      {"interleave", &t.interleave, 0, 1, false},
-      {"persist_split", &t.persist_split, 0, 1, false},
-      {"net_mix", &t.net_mix, 0, 1, false},
-      {"rss_level_cap", &t.rss_level_cap, 1, 8, false},
-      {"large_sort", &t.large_sort, 0, 1, false},
+static const std::vector<TuneEntry>& tune_table() {
+  static const std::vector<TuneEntry> table = {
+      {"family", &Tuning::family, 0, 2, false, true},
+      {"rss_k_small", nullptr, 4, 16, true, true},
+      {"rss_k_mid", nullptr, 4, 32, true, true},
+      {"rss_k_large", nullptr, 4, 64, true, true},
+      {"rss_bound_small", &Tuning::rss_bound_small, 16, 64, false, true},
+      {"rss_bound_mid", &Tuning::rss_bound_mid, 16, 128, false, true},
+      {"rss_oversample", &Tuning::rss_oversample, 1, 4, false, true},
+      {"fixed_apt", &Tuning::fixed_apt, 1, 4, false, true},
+      {"persist_occ", &Tuning::persist_occ, 0, 16, false, false},
+      {"rss_rounds", &Tuning::rss_rounds, 1, 64, false, false},
+      {"interleave", &Tuning::interleave, 0, 1, false, false},
+      {"persist_split", &Tuning::persist_split, 0, 1, false, false},
+      {"net_mix", &Tuning::net_mix, 0, 1, false, false},
+      {"rss_level_cap", &Tuning::rss_level_cap, 1, 8, false, false},
+      {"large_sort", &Tuning::large_sort, 0, 1, false, false},
   };
+  return table;
+}
+
+static int& slot_of(Tuning& t, const TuneEntry& e) {
+  if (e.slot) return t.*(e.slot);
+  // the three first-level bucket counts share an array
+  return t.rss_k[e.name[6] == 's' ? 0 : (e.name[6] == 'm' ? 1 : 2)];
+}
+
+// name = "<knob>" (every key width) or "u32.<knob>" / "u64.<knob>" (one width
+// of a per-width knob).  Returns the entry and the widths it addresses.
+static const TuneEntry* find_knob(const char* name, bool& w32, bool& w64) {
+  if (!name) return nullptr;
+  w32 = w64 = true;
+  if (std::strncmp(name, "u32.", 4) == 0) {
+    w64 = false;
+    name += 4;
+  } else if (std::strncmp(name, "u64.", 4) == 0) {
+    w32 = false;
+    name += 4;
+  }
+  for (const TuneEntry& e : tune_table())
+    if (std::strcmp(e.name, name) == 0) return (e.per_width || (w32 && w64)) ? &e : nullptr;
+  return nullptr;
+}
+
+static bool valid_value(const TuneEntry& e, int64_t value, const Tuning& t) {
+  if (value < e.lo || value > e.hi) return false;
+  if (e.pow2_k && (value & (value - 1)) != 0) return false;
+  if (e.slot == &Tuning::fixed_apt && value == 3) return false;
+  // a 16-lane group holds at most 64 keys, a 32-lane group 128; bound_mid >= bound_small
+  if (e.slot == &Tuning::rss_bound_mid && value < t.rss_bound_small) return false;
+  if (e.slot == &Tuning::rss_bound_small && value > t.rss_bound_mid) return false;
+  return true;
 }
 
 static ss_status set_tuning(const char* name, int64_t value) {
-  if (!name) return SS_ENOTUNE;
+  bool w32, w64;
+  const TuneEntry* e = find_knob(name, w32, w64);
+  if (!e) return SS_ENOTUNE;
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  for (const TuneEntry& e : tune_table()) {
-    if (std::strcmp(e.name, name) != 0) continue;
-    if (value < e.lo || value > e.hi) return SS_EINVAL;
-    if (e.pow2_k && (value & (value - 1)) != 0) return SS_EINVAL;
-    *e.slot = (int)value;
-    return SS_OK;
-  }
-  return SS_ENOTUNE;
+  for (int w = 0; w < 2; ++w)
+    if ((w == 0 ? w32 : w64) && !valid_value(*e, value, g_tuning[w])) return SS_EINVAL;
+  for (int w = 0; w < 2; ++w)
+    if (w == 0 ? w32 : w64) slot_of(g_tuning[w], *e) = (int)value;
+  return SS_OK;
 }
 
 }  // namespace ss
@@ -353,11 +390,15 @@ ss_status ss_stream_copy(void* dst, const void* src, int64_t bytes, void* stream
 ss_status ss_set_tuning_value(const char* name, int64_t value) { return set_tuning(name, value); }
 
 int64_t ss_get_tuning_value(const char* name) {
-  if (!name) return -1;
+  bool w32, w64;
+  const TuneEntry* e = find_knob(name, w32, w64);
+  if (!e) return -1;
   std::lock_guard<std::mutex> lock(g_tune_mu);
-  for (const TuneEntry& e : tune_table())
-    if (std::strcmp(e.name, name) == 0) return *e.slot;
-  return -1;
+  if (w32 && w64) {  // one value for every width, or -2 if the widths differ
+    const int a = slot_of(g_tuning[0], *e), b = slot_of(g_tuning[1], *e);
+    return a == b ? a : -2;
+  }
+  return slot_of(g_tuning[w32 ? 0 : 1], *e);
 }
 
 // Minimal reader for a flat JSON object of integer values: {"a": 1, "b": 2}.

@@ -34,12 +34,14 @@ constexpr int kTileThreads = 256;
 // non-temporal builtins).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int N, class K> struct TileLayout {
+// Tile of TA = A * 256 arrays (A arrays per thread).
+template <int N, class K, int A = 1> struct TileLayout {
+  static constexpr int TA = A * kTileThreads;
   static constexpr int E = (int)sizeof(K);
   static constexpr bool kVec = (N * E) % 16 == 0;
   static constexpr int C = kVec ? N * E / 16 : 1;   // 16-byte chunks per array
   static constexpr int P = (N % 2) ? N : N + 1;    // element pitch (element layout)
-  static constexpr int kBytes = kVec ? kTileThreads * N * E : kTileThreads * P * E;
+  static constexpr int kBytes = kVec ? TA * N * E : TA * P * E;
   static constexpr int kPerChunk = 16 / E;         // keys per 16-byte chunk
   // Rotation step: threads a and a' whose rows start in the same bank group
   // within one 8-thread pass get different rotations.
@@ -65,6 +67,11 @@ template <int N, class K> struct TileLayout {
   }
 };
 
+// Arrays per thread that a tile may use: the tile's LDS stays within 32 KiB
+// (so that the work-groups of one CU keep enough waves to hide HBM latency).
+template <int N, class K, int A>
+constexpr bool tile_fits() { return TileLayout<N, K, A>::kBytes <= 32768; }
+
 template <class K> __device__ __forceinline__ K lds_ld(const unsigned char* p) {
   return *reinterpret_cast<const K*>(p);
 }
@@ -72,21 +79,22 @@ template <class K> __device__ __forceinline__ void lds_st(unsigned char* p, K v)
   *reinterpret_cast<K*>(p) = v;
 }
 
-template <int F, int N, class K>
+template <int F, int N, class K, int A>
 __global__ void __launch_bounds__(kTileThreads)
 fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
-  using L = TileLayout<N, K>;
+  using L = TileLayout<N, K, A>;
+  constexpr int TA = L::TA;
   __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
-  constexpr int kChunks = kTileThreads * N * L::E / 16;  // 16-byte chunks in a full tile
+  constexpr int kChunks = TA * N * L::E / 16;  // 16-byte chunks in a full tile
   constexpr int kIters = (kChunks + kTileThreads - 1) / kTileThreads;
   constexpr bool kExact = (kChunks % kTileThreads) == 0;
 
   const int t = threadIdx.x;
-  const int64_t first = (int64_t)blockIdx.x * kTileThreads;
+  const int64_t first = (int64_t)blockIdx.x * TA;
   const int64_t left = count - first;
-  const int valid = left < kTileThreads ? (int)left : kTileThreads;
+  const int valid = left < TA ? (int)left : TA;
   K* gk = keys + first * N;
-  const bool full = valid == kTileThreads;
+  const bool full = valid == TA;
 
   if (full) {
     const u32x4* g4 = reinterpret_cast<const u32x4*>(gk);
@@ -124,33 +132,37 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
   }
   __syncthreads();
 
-  if (t < valid) {
-    K r[N];
-    if constexpr (L::kVec) {
 #pragma unroll
-      for (int k = 0; k < L::C; ++k) {
-        u32x4 q = *reinterpret_cast<const u32x4*>(lds + L::chunk_slot(t, k) * 16);
-        __builtin_memcpy(&r[k * L::kPerChunk], &q, 16);
+  for (int q = 0; q < A; ++q) {
+    const int a = t + q * kTileThreads;  // this thread's q-th array of the tile
+    if (a < valid) {
+      K r[N];
+      if constexpr (L::kVec) {
+#pragma unroll
+        for (int k = 0; k < L::C; ++k) {
+          u32x4 v = *reinterpret_cast<const u32x4*>(lds + L::chunk_slot(a, k) * 16);
+          __builtin_memcpy(&r[k * L::kPerChunk], &v, 16);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[j] = lds_ld<K>(lds + L::elem_offset(a, j));
       }
-    } else {
 #pragma unroll
-      for (int j = 0; j < N; ++j) r[j] = lds_ld<K>(lds + L::elem_offset(t, j));
-    }
+      for (int j = 0; j < N; ++j) r[j] = flip.enc(r[j]);
+      net_sort<F, N>(r);
 #pragma unroll
-    for (int j = 0; j < N; ++j) r[j] = flip.enc(r[j]);
-    net_sort<F, N>(r);
+      for (int j = 0; j < N; ++j) r[j] = flip.dec(r[j]);
+      if constexpr (L::kVec) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) r[j] = flip.dec(r[j]);
-    if constexpr (L::kVec) {
+        for (int k = 0; k < L::C; ++k) {
+          u32x4 v;
+          __builtin_memcpy(&v, &r[k * L::kPerChunk], 16);
+          *reinterpret_cast<u32x4*>(lds + L::chunk_slot(a, k) * 16) = v;
+        }
+      } else {
 #pragma unroll
-      for (int k = 0; k < L::C; ++k) {
-        u32x4 q;
-        __builtin_memcpy(&q, &r[k * L::kPerChunk], 16);
-        *reinterpret_cast<u32x4*>(lds + L::chunk_slot(t, k) * 16) = q;
+        for (int j = 0; j < N; ++j) lds_st<K>(lds + L::elem_offset(a, j), r[j]);
       }
-    } else {
-#pragma unroll
-      for (int j = 0; j < N; ++j) lds_st<K>(lds + L::elem_offset(t, j), r[j]);
     }
   }
   __syncthreads();
@@ -202,14 +214,30 @@ fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, KeyMap<
   for (int j = 0; j < N; ++j) p[j] = flip.dec(r[j]);
 }
 
+template <int F, int N, class K, int A>
+static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_t s) {
+  constexpr int64_t TA = (int64_t)A * kTileThreads;
+  const int64_t blocks = (count + TA - 1) / TA;
+  if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fixed_tile_kernel<F, N, K, A>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s, keys, count,
+                     flip);
+  return hipGetLastError();
+}
+
 template <int F, int N, class K>
-static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
+static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, int apt, hipStream_t s) {
   const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
   if (tiled) {
-    hipLaunchKernelGGL((fixed_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s,
-                       keys, count, flip);
+    // arrays per thread: the tuned value, or the largest smaller one whose tile fits
+    if constexpr (tile_fits<N, K, 4>()) {
+      if (apt >= 4) return launch_tile<F, N, K, 4>(keys, count, flip, s);
+    }
+    if constexpr (tile_fits<N, K, 2>()) {
+      if (apt >= 2) return launch_tile<F, N, K, 2>(keys, count, flip, s);
+    }
+    return launch_tile<F, N, K, 1>(keys, count, flip, s);
   } else {
     hipLaunchKernelGGL((fixed_direct_kernel<F, N, K>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s,
                        keys, count, stride, flip);
@@ -219,22 +247,23 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<
 
 template <int F, class K>
 static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
+  const int apt = tuning(sizeof(K)).fixed_apt;
   switch (n) {
-    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, s);
-    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, s);
-    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, s);
-    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, s);
-    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, s);
-    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, s);
-    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, s);
-    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, s);
-    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, s);
-    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, s);
-    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, s);
-    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, s);
-    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, s);
-    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, s);
-    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, s);
+    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, s);
+    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, s);
+    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, s);
+    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, s);
+    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, s);
+    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, s);
+    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, s);
+    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, s);
+    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, s);
+    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, s);
+    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, s);
+    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, s);
+    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, s);
+    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, s);
+    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -271,7 +300,7 @@ hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, hipStre
 
 hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,
                             hipStream_t s) {
-  switch (tuning().family) {
+  switch (tuning(sizeof(*keys)).family) {
     case 1: return launch_fixed_f<1>(keys, n, count, stride, flip, s);
     case kFamilyInsertion: return launch_fixed_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
     default: return launch_fixed_f<0>(keys, n, count, stride, flip, s);
@@ -279,7 +308,7 @@ hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride
 }
 hipError_t launch_fixed_u64(uint64_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint64_t> flip,
                             hipStream_t s) {
-  switch (tuning().family) {
+  switch (tuning(sizeof(*keys)).family) {
     case 1: return launch_fixed_f<1>(keys, n, count, stride, flip, s);
     case kFamilyInsertion: return launch_fixed_f<kFamilyInsertion>(keys, n, count, stride, flip, s);
     default: return launch_fixed_f<0>(keys, n, count, stride, flip, s);

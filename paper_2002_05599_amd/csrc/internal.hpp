@@ -19,8 +19,14 @@ struct Tuning {
   int net_mix = 0;        // 1: persistent forms sort 2..16-key segments in batch order, mixed sizes
   int rss_level_cap = 8;  // RSS levels before the rank-counting fallback finishes a pending bucket
   int large_sort = 0;     // 17..256 keys: 0 Register Sample Sort, 1 insertion sort (the IS+SN hybrid)
+  int rss_bound_small = 64;  // largest segment sorted by a 16-lane RSS group (16..64)
+  int rss_bound_mid = 128;   // largest segment sorted by a 32-lane RSS group (bound_small..128)
+  int rss_oversample = 3;    // oversampling a of the RSS levels with 4 buckets (1..4)
+  int fixed_apt = 1;         // arrays per thread of the fixed-layout network kernels (1, 2, 4)
 };
-Tuning tuning();  // a consistent copy of the current settings
+// A consistent copy of the current settings for keys of key_bytes (4 or 8)
+// bytes: the variant choices are kept per key width.
+Tuning tuning(int key_bytes);
 
 // Fixed layout, n = 2..16 (networks).  flip = the key type's order-preserving map.
 hipError_t launch_fixed_u32(uint32_t* keys, int n, int64_t count, int64_t stride, KeyMap<uint32_t> flip,

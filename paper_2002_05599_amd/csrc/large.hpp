@@ -37,7 +37,7 @@ template <class K, int V> struct LargeLds {
 // work-group; every thread of the work-group must call this.
 template <int F, class K, int V>
 __device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv, int m, KeyMap<K> flip, int k0,
-                                           int level_cap) {
+                                           RssCfg cfg) {
   using LL = LargeLds<K, V>;
   using VT = Pay<V>;
   K* key_buf[2] = {reinterpret_cast<K*>(lds), reinterpret_cast<K*>(lds + LL::kBufBytes)};
@@ -54,7 +54,7 @@ __device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv
     const int len = min(kRunN, m - lo);
     rss_group_load(*group, gk + lo, V ? gv + lo : nullptr, len, flip);
     wave_lds_sync();
-    rss_group_sort_lds<F>(*group, len, k0, level_cap);
+    rss_group_sort_lds<F>(*group, len, k0, cfg);
     for (int i = lane; i < len; i += kWave) {
       key_buf[0][lo + i] = group->key[i];
       if constexpr (V) val_buf[0][lo + i] = group->val[i];

@@ -52,6 +52,14 @@ namespace ss {
 
 constexpr int kLevelCap = 8;
 
+// Run-time choices of the recursion: levels before the rank-counting
+// fallback (1..kLevelCap) and the oversampling factor a of the levels with
+// k = 4 buckets (1..4: a sample of 4a keys, splitters at ranks a, 2a, 3a).
+struct RssCfg {
+  int level_cap;
+  int a4;
+};
+
 template <class K, int V, int G> struct GroupLds {
   static constexpr int kCap = 4 * G;          // keys per array handled by a G-lane group
   static constexpr int kMaxPend = kCap / 17;  // buckets with more than 16 keys
@@ -253,10 +261,11 @@ __device__ __forceinline__ K team_sort(K x, int t) {
 // key), sorted across the team; also clears the bucket's child counters and
 // records whether all of its k-1 splitters are equal.
 template <int KB, class K, int V, int G>
-__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
-  constexpr int A = oversampling(KB);
-  constexpr int NS = A * KB;
-  constexpr int T = NS <= 16 ? 16 : NS;   // team size, a power of two
+__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np, int a4) {
+  // k = 4: the tuned oversampling (a team of 16 lanes holds up to 16 samples)
+  const int A = KB == 4 ? a4 : oversampling(KB);
+  const int NS = A * KB;
+  constexpr int T = oversampling(KB) * KB <= 16 ? 16 : oversampling(KB) * KB;  // team size, a power of two
   constexpr int PER = G / T;              // buckets sampled per pass
   constexpr int kSpan = KB > 16 ? KB : 16;
   static_assert(PER >= 1 && T * PER == G, "team must divide the group");
@@ -285,8 +294,8 @@ __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int 
 // #{i = 1..k-1 : s_i < e} for the splitters s_i = smp[A*i - 1] of a sorted
 // sample held in LDS: a branch-free binary search (the in-memory splitter
 // tree of super scalar sample sort that the paper's register tree replaces).
-template <int LOGK, int A, class K>
-__device__ __forceinline__ int lds_bucket(K e, const K* smp) {
+template <int LOGK, class K>
+__device__ __forceinline__ int lds_bucket(K e, const K* smp, int A) {
   int j = 0;
 #pragma unroll
   for (int step = (1 << LOGK) / 2; step >= 1; step >>= 1) {
@@ -316,9 +325,10 @@ __device__ __forceinline__ int three_way(K e, K v) {
 // list, in position order) and every key is written to bucket start + child
 // offset + rank, together with its next-level bucket id.
 template <int LOGK, bool kFirst, class K, int V, int G>
-__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
+__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn,
+                                            int a4) {
   constexpr int k = 1 << LOGK;
-  constexpr int a = oversampling(k);
+  const int a = k == 4 ? a4 : oversampling(k);
   constexpr int kSpan = k > 16 ? k : 16;  // entries per bucket in cnt/nextpb
   static_assert(kFirst || k <= 16, "only the first level has more than 16 children");
   static_assert(kSpan <= G, "the children of a bucket are scanned in one pass");
@@ -364,12 +374,12 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], spl[0]);
     } else if constexpr (kFirst) {
       const K* smp = &L.sample[0];
-      cc = lds_bucket<LOGK, a>(e[s], smp);
+      cc = lds_bucket<LOGK>(e[s], smp, a);
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], smp[a - 1]);
     } else {
       const int q = ok ? pp : 0;
       const K* smp = &L.sample[q * 16];
-      cc = lds_bucket<LOGK, a>(e[s], smp);
+      cc = lds_bucket<LOGK>(e[s], smp, a);
       const bool dg = L.deg[q] != 0;
       if (ballot(dg) != 0ull && dg) cc = three_way(e[s], smp[a - 1]);
     }
@@ -483,7 +493,7 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
 // wave-uniform).  k0: first-level bucket count; level_cap (1..kLevelCap):
 // levels of sample sort before the rank-counting fallback.
 template <int F, class K, int V, int G>
-__device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0, int level_cap) {
+__device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0, RssCfg cfg) {
   const int gl = lane_id() % G;
   int np = m > 16 ? 1 : 0;
   int nf = (m >= 2 && m <= 16) ? 1 : 0;
@@ -498,7 +508,7 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
 
   int cur = 0;
   for (int level = 0; ballot(np > 0) != 0ull; ++level) {
-    if (level == level_cap) {
+    if (level == cfg.level_cap) {
       rank_sort_pending(L, cur, np);
       break;
     }
@@ -506,32 +516,32 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
     int npn = 0;
     if (kk == 64) {
       if constexpr (max_first_k(G) >= 64) {
-        sample_phase<64>(L, cur, np);
+        sample_phase<64>(L, cur, np, cfg.a4);
         wave_lds_sync();
-        split_level<6, true>(L, m, cur, np, nf, npn);
+        split_level<6, true>(L, m, cur, np, nf, npn, cfg.a4);
       }
     } else if (kk == 32) {
       if constexpr (max_first_k(G) >= 32) {
-        sample_phase<32>(L, cur, np);
+        sample_phase<32>(L, cur, np, cfg.a4);
         wave_lds_sync();
-        split_level<5, true>(L, m, cur, np, nf, npn);
+        split_level<5, true>(L, m, cur, np, nf, npn, cfg.a4);
       }
     } else if (kk == 16) {
-      sample_phase<16>(L, cur, np);
+      sample_phase<16>(L, cur, np, cfg.a4);
       wave_lds_sync();
-      split_level<4, true>(L, m, cur, np, nf, npn);
+      split_level<4, true>(L, m, cur, np, nf, npn, cfg.a4);
     } else if (kk == 8) {
-      sample_phase<8>(L, cur, np);
+      sample_phase<8>(L, cur, np, cfg.a4);
       wave_lds_sync();
-      split_level<3, true>(L, m, cur, np, nf, npn);
+      split_level<3, true>(L, m, cur, np, nf, npn, cfg.a4);
     } else if (level == 0) {
-      sample_phase<4>(L, cur, np);
+      sample_phase<4>(L, cur, np, cfg.a4);
       wave_lds_sync();
-      split_level<2, true>(L, m, cur, np, nf, npn);
+      split_level<2, true>(L, m, cur, np, nf, npn, cfg.a4);
     } else {
-      sample_phase<4>(L, cur, np);
+      sample_phase<4>(L, cur, np, cfg.a4);
       wave_lds_sync();
-      split_level<2, false>(L, m, cur, np, nf, npn);
+      split_level<2, false>(L, m, cur, np, nf, npn, cfg.a4);
     }
     np = npn;
     cur ^= 1;
@@ -583,10 +593,10 @@ __device__ __forceinline__ void rss_group_store(GroupLds<K, V, G>& L, K* gk, Pay
 // store.
 template <int F, class K, int V, int G>
 __device__ __forceinline__ void rss_group_sort(GroupLds<K, V, G>& L, K* gk, Pay<V>* gv, int m, KeyMap<K> flip, int k0,
-                                               int level_cap) {
+                                               RssCfg cfg) {
   rss_group_load(L, gk, gv, m, flip);
   wave_lds_sync();
-  rss_group_sort_lds<F>(L, m, k0, level_cap);
+  rss_group_sort_lds<F>(L, m, k0, cfg);
   rss_group_store(L, gk, gv, m, flip);
   wave_lds_sync();
 }

@@ -63,11 +63,14 @@ constexpr int kCtrlTile = 128;       // tile counters: kind set k, partition p a
 constexpr int kTileParts = 8;        // counter partitions (one 128-byte line each)
 constexpr int kCtrlWords = kCtrlTile + 6 * kTileParts * 32;  // 6 kind sets
 
-__device__ __forceinline__ int size_class(int sz) {
+// bs, bm: the largest sizes given to 16- and 32-lane RSS groups (tuned:
+// bs in 16..64, bm in bs..128; a 16-lane group holds up to 64 keys, a 32-lane
+// group up to 128).
+__device__ __forceinline__ int size_class(int sz, int bs, int bm) {
   if (sz < 2) return sz >= 0 ? -1 : -3;  // -1: nothing to do, -3: bad offsets
   if (sz <= 16) return sz - 2;
-  if (sz <= 64) return 15;
-  if (sz <= 128) return 16;
+  if (sz <= bs) return 15;
+  if (sz <= bm) return 16;
   if (sz <= kMaxN) return 17;
   if (sz <= kMaxLargeN) return kLargeClass;
   return -2;  // too big
@@ -104,17 +107,21 @@ __host__ __device__ __forceinline__ int class_at(int order) {
 // --- binning kernels (segmented_common.hip) -----------------------------------
 
 __global__ void seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg,
-                                 uint32_t* __restrict__ blockhist, int* status, int mix);
+                                 uint32_t* __restrict__ blockhist, int* status, int bins);
 __global__ void seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restrict__ ctrl);
 __global__ void seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg,
                                    const uint32_t* __restrict__ blockbase, const uint32_t* __restrict__ ctrl,
-                                   int32_t* __restrict__ ids, int mix);
+                                   int32_t* __restrict__ ids, int bins);
 
-// Size class used by the binning: with `mix`, every network size goes to
-// class 0, whose segments are then sorted in batch order (see net_tile_mixed).
-__device__ __forceinline__ int bin_class(int sz, int mix) {
-  const int c = size_class(sz);
-  return (mix && c > 0 && c < kNetClasses) ? 0 : c;
+// The binning's parameters in one word: bit 0 = every network size goes to
+// class 0, whose segments are then sorted in batch order (see
+// net_tile_mixed); bits 8..15 and 16..23 = the RSS class bounds bs and bm.
+__host__ __device__ __forceinline__ int pack_bins(int mix, int bs, int bm) {
+  return (mix ? 1 : 0) | (bs << 8) | (bm << 16);
+}
+__device__ __forceinline__ int bin_class(int sz, int bins) {
+  const int c = size_class(sz, (bins >> 8) & 0xFF, (bins >> 16) & 0xFF);
+  return ((bins & 1) && c > 0 && c < kNetClasses) ? 0 : c;
 }
 
 // --- tile handlers -----------------------------------------------------------
@@ -248,7 +255,7 @@ template <int F, class K, int V, int G>
 __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V>* vals,
                                          const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
                                          int list, int count, int first, int rounds, KeyMap<K> flip, int k0,
-                                         int level_cap) {
+                                         RssCfg cfg) {
   constexpr int kGroups = kWave / G;
   auto* L = reinterpret_cast<GroupLds<K, V, G>*>(wave_lds);
   const int lane = lane_id();
@@ -303,7 +310,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V
       bounds(r + 1, lo_n, m_n);
       fetch(lo_n, m_n);
     }
-    rss_group_sort_lds<F>(L[g], m, k0, level_cap);
+    rss_group_sort_lds<F>(L[g], m, k0, cfg);
     rss_group_store(L[g], keys + lo, V ? vals + lo : nullptr, m, flip);
     wave_lds_sync();
     lo = lo_n;
@@ -336,8 +343,10 @@ struct SortArgs {
   int k0[3];
   int interleave;  // alternate RSS and network tiles in the persistent kernel
   int net_mix;     // class 0 holds every network size, in batch order
-  int level_cap;   // RSS levels before the rank-counting fallback
+  RssCfg cfg;   // RSS levels before the rank-counting fallback
   int large_sort;  // 1: the RSS classes are sorted by insertion sort (IS+SN)
+  int bound_small;  // largest segment of the 16-lane RSS class
+  int bound_mid;    // largest segment of the 32-lane RSS class
 };
 
 // Kind sets of the persistent kernels: every class (one kernel holding every
@@ -380,17 +389,17 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, Pay<V
   if constexpr (KS == kKindAll || KS == kKindRss16) {
     if (c == 15)
       rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0],
-                            a.level_cap);
+                            a.cfg);
   }
   if constexpr (KS == kKindAll || KS == kKindRss32) {
     if (c == 16)
       rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1],
-                            a.level_cap);
+                            a.cfg);
   }
   if constexpr (KS == kKindAll || KS == kKindRss64) {
     if (c == 17)
       rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2],
-                            a.level_cap);
+                            a.cfg);
   }
 }
 
@@ -501,7 +510,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
         is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, u * kGroups, n * kGroups, flip);
       else
         rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0,
-                             a.level_cap);
+                             a.cfg);
     };
     const int units = (count + kGroups - 1) / kGroups;
     const int R = class_rounds(kClass, count, a.rounds, waves, kPersistTpw);
@@ -606,13 +615,13 @@ seg_class_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, Ke
     is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, first, class_tile(c, rounds), flip);
   } else if constexpr (KIND == 1) {
     rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[0], a.level_cap);
+                          a.k0[0], a.cfg);
   } else if constexpr (KIND == 2) {
     rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[1], a.level_cap);
+                          a.k0[1], a.cfg);
   } else {
     rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[2], a.level_cap);
+                          a.k0[2], a.cfg);
   }
 }
 
@@ -634,7 +643,7 @@ seg_large_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, Ke
       if (threadIdx.x == 0) insertion_sort_global<K, V>(keys + lo, V ? vals + lo : nullptr, m, flip);
       continue;
     }
-    large_sort<F, K, V>(large_lds, keys + lo, V ? vals + lo : nullptr, m, flip, a.k0[2], a.level_cap);
+    large_sort<F, K, V>(large_lds, keys + lo, V ? vals + lo : nullptr, m, flip, a.k0[2], a.cfg);
   }
 }
 
@@ -689,7 +698,7 @@ hipError_t ensure_workspace(SegmentedCache* ws, int32_t nseg, hipStream_t s);
 
 template <int F, class K, int V, int KS>
 static int persistent_blocks(DeviceCtx* c) {
-  int occ = tuning().persist_occ;
+  int occ = tuning(sizeof(K)).persist_occ;
   if (occ <= 0) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_persistent_kernel<F, K, V, KS>, kSortThreads, 0) !=
@@ -702,8 +711,9 @@ static int persistent_blocks(DeviceCtx* c) {
   return max(occ * c->num_cus, kTileParts);
 }
 
+template <class K>
 inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
-  const Tuning t = tuning();
+  const Tuning t = tuning(sizeof(K));
   SortArgs a;
   a.offsets = offsets;
   a.ids = s.ids;
@@ -715,7 +725,9 @@ inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
   a.k0[2] = t.rss_k[2];
   a.interleave = t.interleave;
   a.net_mix = t.net_mix;
-  a.level_cap = t.rss_level_cap;
+  a.bound_small = t.rss_bound_small;
+  a.bound_mid = t.rss_bound_mid;
+  a.cfg = RssCfg{t.rss_level_cap, t.rss_oversample};
   a.large_sort = t.large_sort;
   return a;
 }
@@ -739,7 +751,8 @@ struct SegLaunch {
   Pay<V>* vals;
   SortArgs args;
   KeyMap<K> flip;
-  int mix;  // binning mixes the network sizes (persistent forms only)
+  int mix;   // binning mixes the network sizes (persistent forms only)
+  int bins;  // pack_bins(mix, RSS class bounds): the binning kernels' parameter
   void* p_count[5];
   void* p_scan[3];
   void* p_scatter[6];
@@ -769,13 +782,14 @@ struct SegLaunch {
     ids = s.ids;
     keys = k;
     vals = v;
-    args = make_args(off, s);
+    args = make_args<K>(off, s);
     flip = fl;
     mix = args.net_mix;
-    p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status; p_count[4] = &mix;
+    bins = pack_bins(mix, args.bound_small, args.bound_mid);
+    p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status; p_count[4] = &bins;
     p_scan[0] = &blockhist; p_scan[1] = &nblocks; p_scan[2] = &ctrl;
     p_scatter[0] = &offsets; p_scatter[1] = &nseg; p_scatter[2] = &blockbase; p_scatter[3] = &ctrl_c;
-    p_scatter[4] = &ids; p_scatter[5] = &mix;
+    p_scatter[4] = &ids; p_scatter[5] = &bins;
     p_sort[0] = &keys; p_sort[1] = &vals; p_sort[2] = &args; p_sort[3] = &ctrl; p_sort[4] = &flip;
     p_sort_large[0] = &keys; p_sort_large[1] = &vals; p_sort_large[2] = &args; p_sort_large[3] = &flip;
   }
@@ -836,10 +850,10 @@ struct SegLaunch {
 
   hipError_t launch_binning(hipStream_t s) {
     hipLaunchKernelGGL(seg_count_kernel, dim3(kBinBlocks), dim3(kBinThreads), 0, s, offsets, nseg, blockhist,
-                       status, mix);
+                       status, bins);
     hipLaunchKernelGGL(seg_scan_kernel, dim3(1), dim3(1024), 0, s, blockhist, nblocks, ctrl);
     hipLaunchKernelGGL(seg_scatter_kernel, dim3(kBinBlocks), dim3(kBinThreads), 0, s, offsets, nseg, blockbase,
-                       ctrl_c, ids, mix);
+                       ctrl_c, ids, bins);
     return hipGetLastError();
   }
   hipError_t launch_direct(hipStream_t s) {
@@ -865,6 +879,7 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
   L.args.waves = nb * c->num_cus * kSortWaves;
   L.args.net_mix = 0;  // the baseline launches one kernel per network size
   L.mix = 0;
+  L.bins = pack_bins(0, L.args.bound_small, L.args.bound_mid);
   hipError_t e = L.launch_binning(s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, (kCtrlStart + kClasses) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -937,7 +952,7 @@ static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream
 
 template <int F, class K, int V>
 static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
-  L.split = tuning().persist_split != 0;
+  L.split = tuning(sizeof(K)).persist_split != 0;
   for (int& b : L.persist_blocks) b = 0;
   if (L.split) {
     L.persist_blocks[kKindNet] = persistent_blocks<F, K, V, kKindNet>(c);
@@ -1024,7 +1039,7 @@ static int segmented_pick(DeviceCtx* c, SegmentedCache* ws, const SegBuffers* b,
 template <class K>
 static int segmented_family(DeviceCtx* c, SegmentedCache* ws, const SegBuffers* b, K* keys, void* vals, int vbytes,
                             const int32_t* offsets, int32_t nseg, KeyMap<K> flip, int mode, hipStream_t s) {
-  switch (tuning().family) {
+  switch (tuning(sizeof(K)).family) {
     case 1: return segmented_pick<1, K>(c, ws, b, keys, vals, vbytes, offsets, nseg, flip, mode, s);
     case kFamilyInsertion:
       return segmented_pick<kFamilyInsertion, K>(c, ws, b, keys, vals, vbytes, offsets, nseg, flip, mode, s);

@@ -5,7 +5,7 @@ namespace ss {
 
 __global__ void __launch_bounds__(kBinThreads)
 seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg, uint32_t* __restrict__ blockhist,
-                 int* status, int mix) {
+                 int* status, int bins) {
   __shared__ uint32_t hist[kClasses];
   if (threadIdx.x < kClasses) hist[threadIdx.x] = 0;
   __syncthreads();
@@ -15,7 +15,7 @@ seg_count_kernel(const int32_t* __restrict__ offsets, int32_t nseg, uint32_t* __
     for (int q = 0; q < kBinItems; ++q) {
       const int64_t i = base + q * kBinThreads + threadIdx.x;
       if (i < nseg) {
-        const int c = bin_class(offsets[i + 1] - offsets[i], mix);
+        const int c = bin_class(offsets[i + 1] - offsets[i], bins);
         if (c >= 0)
           atomicAdd(&hist[c], 1u);
         else if (c < -1)
@@ -76,7 +76,7 @@ seg_scan_kernel(uint32_t* __restrict__ blockhist, int nblocks, uint32_t* __restr
 
 __global__ void __launch_bounds__(kBinThreads)
 seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint32_t* __restrict__ blockbase,
-                   const uint32_t* __restrict__ ctrl, int32_t* __restrict__ ids, int mix) {
+                   const uint32_t* __restrict__ ctrl, int32_t* __restrict__ ids, int bins) {
   __shared__ uint32_t cur[kClasses];
   if (threadIdx.x < kClasses)
     cur[threadIdx.x] = ctrl[kCtrlStart + threadIdx.x] + blockbase[threadIdx.x * kBinBlocks + blockIdx.x];
@@ -86,7 +86,7 @@ seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint
     for (int q = 0; q < kBinItems; ++q) {
       const int64_t i = base + q * kBinThreads + threadIdx.x;
       if (i < nseg) {
-        const int c = bin_class(offsets[i + 1] - offsets[i], mix);
+        const int c = bin_class(offsets[i + 1] - offsets[i], bins);
         if (c >= 0) ids[atomicAdd(&cur[c], 1u)] = (int32_t)i;
       }
     }

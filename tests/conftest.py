@@ -7,9 +7,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# every tuning knob the library exposes (include/smallsort.h)
-TUNING_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "persist_occ", "rss_rounds",
-                "interleave", "persist_split", "net_mix", "rss_level_cap", "large_sort")
+# every tuning knob the library exposes (include/smallsort.h); the per-width
+# ones are snapshot per width
+PER_WIDTH_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "rss_bound_small", "rss_bound_mid",
+                   "rss_oversample", "fixed_apt")
+GLOBAL_KNOBS = ("persist_occ", "rss_rounds", "interleave", "persist_split", "net_mix", "rss_level_cap",
+                "large_sort")
+TUNING_KNOBS = tuple(f"{w}.{k}" for k in PER_WIDTH_KNOBS for w in ("u32", "u64")) + GLOBAL_KNOBS
 
 
 def pytest_configure(config):
@@ -27,6 +31,14 @@ def _restore_tuning():
         return
     before = {k: ss.get_tuning(k) for k in TUNING_KNOBS}
     yield
+    # bounds first lowered then raised in an order that keeps small <= mid valid
+    for k in sorted(before, key=lambda k: (not k.endswith("rss_bound_mid"), k)):
+        v = before[k]
+        if v >= 0 and ss.get_tuning(k) != v:
+            try:
+                ss.set_tuning(k, v)
+            except ss.SmallSortError:
+                pass
     for k, v in before.items():
         if v >= 0 and ss.get_tuning(k) != v:
             ss.set_tuning(k, v)

@@ -52,13 +52,20 @@ class tuned:
 
     def __enter__(self):
         import paper_2002_05599_amd as ss
-        self.old = {k: ss.get_tuning(k) for k in self.knobs}
+        self.old = {}
+        for k in self.knobs:  # per-width knobs are restored per width
+            for name in ((f"u32.{k}", f"u64.{k}") if ss.get_tuning(f"u32.{k}") >= 0 else (k,)):
+                self.old[name] = ss.get_tuning(name)
         for k, v in self.knobs.items():
             ss.set_tuning(k, v)
         return self
 
     def __exit__(self, *exc):
         import paper_2002_05599_amd as ss
-        for k, v in self.old.items():
-            ss.set_tuning(k, v)
+        for _ in range(2):  # twice: a bound may only be valid once the other is back
+            for k, v in self.old.items():
+                try:
+                    ss.set_tuning(k, v)
+                except ss.SmallSortError:
+                    pass
         return False

@@ -149,3 +149,29 @@ def test_device_sort_workspace_size(lib):
             assert n * (kb + vb) <= w <= 1.2 * n * (kb + vb) + (1 << 20)
             assert f(kt, vb, n // 10) < w
     assert f(2, 8, 1000) > 0
+
+
+def test_per_width_tuning(lib):
+    """Per-width knobs: the plain name sets both widths, a prefixed name one;
+    a plain get of differing widths reads -2; global knobs take no prefix;
+    the lane-group bounds stay ordered."""
+    from helpers import tuned
+    with tuned(family=1, rss_bound_small=64, rss_bound_mid=128):
+        ss.set_tuning("u64.family", 0)
+        assert ss.get_tuning("u32.family") == 1 and ss.get_tuning("u64.family") == 0
+        assert ss.get_tuning("family") == -2
+        ss.set_tuning("family", 2)
+        assert ss.get_tuning("family") == 2
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning("u32.rss_rounds", 8)  # one value for every width
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning("rss_bound_small", 65)  # a 16-lane group holds at most 64 keys
+        ss.set_tuning("rss_bound_mid", 96)
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning("rss_bound_mid", 32)  # below bound_small (64)
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning("fixed_apt", 3)
+        for v in (1, 4):
+            ss.set_tuning("rss_oversample", v)
+        with pytest.raises(ss.SmallSortError):
+            ss.set_tuning("rss_oversample", 5)

@@ -162,3 +162,19 @@ def test_config1_exact():
     got = run_fixed(a, 8, 100_000, 8)
     want = oracle.sort_fixed(a, 8, 100_000, 8)
     assert (got == want).all(), first_mismatch(got, want, 8)
+
+
+@pytest.mark.parametrize("apt", [1, 2, 4])
+@pytest.mark.parametrize("dtype", [np.uint32, np.int64, np.float32], ids=lambda d: np.dtype(d).name)
+def test_arrays_per_thread(apt, dtype):
+    """Tiles of 1, 2 or 4 arrays per thread (reduced where the tile would not
+    fit): several tiles and a ragged tail for every n."""
+    with tuned(fixed_apt=apt):
+        for n in range(2, 17):
+            count = 3 * 1024 + 77
+            a = (inputs.float_keys(dtype, n * count, seed=n) if np.dtype(dtype).kind == "f"
+                 else inputs.fixed_keys(dtype, n, count, "uniform", seed=n))
+            got = run_fixed(a, n, count, n)
+            want = oracle.sort_fixed(a, n, count, n)
+            bits = np.uint32 if a.dtype.itemsize == 4 else np.uint64
+            assert (got.view(bits) == want.view(bits)).all(), f"n={n}: {first_mismatch(got, want, n)}"

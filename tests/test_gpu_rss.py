@@ -87,7 +87,10 @@ def test_rss_every_size_u32():
 TUNINGS = [("rss_k_small", 4), ("rss_k_small", 8), ("rss_k_small", 16),
            ("rss_k_mid", 4), ("rss_k_mid", 8), ("rss_k_mid", 16), ("rss_k_mid", 32),
            ("rss_k_large", 4), ("rss_k_large", 8), ("rss_k_large", 16), ("rss_k_large", 32),
-           ("rss_k_large", 64), ("family", 0), ("family", 1), ("family", 2), ("large_sort", 1)]
+           ("rss_k_large", 64), ("family", 0), ("family", 1), ("family", 2), ("large_sort", 1),
+           ("rss_oversample", 1), ("rss_oversample", 2), ("rss_oversample", 4),
+           ("rss_bound_small", 16), ("rss_bound_small", 32), ("rss_bound_small", 48),
+           ("rss_bound_mid", 96), ("rss_bound_mid", 64)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t[0]}={t[1]}")
@@ -96,11 +99,10 @@ def test_rss_tuning_variants(tuning):
     insertion sort), and insertion sort in place of RSS (large_sort=1, the
     IS+SN hybrid): uniform keys of every class, duplicate-heavy keys
     (three-way splits) and 64-bit keys."""
+    from helpers import tuned
     name, value = tuning
-    old = ss.get_tuning(name)
-    ss.set_tuning(name, value)
-    try:
-        for n in (20, 64, 65, 100, 128, 129, 200, 256):
+    with tuned(**{name: value}):
+        for n in (20, 33, 48, 64, 65, 100, 128, 129, 200, 256):
             a = inputs.random_keys(np.int32, n * 50, seed=n)
             got = run_fixed(a, n, 50, n)
             assert (got == oracle.sort_fixed(a, n, 50, n)).all(), (name, value, n)
@@ -109,8 +111,6 @@ def test_rss_tuning_variants(tuning):
                 got = run_fixed(a, n, 21, n)
                 want = oracle.sort_fixed(a, n, 21, n)
                 assert (got == want).all(), (name, value, n, kind, first_mismatch(got, want, n))
-    finally:
-        ss.set_tuning(name, old)
 
 
 def test_rss_stride_and_repeat():

@@ -193,12 +193,8 @@ def test_config4_full_size_sampled():
 def test_first_level_bucket_counts_with_payload(k, mode):
     """Every first-level bucket count on the RSS classes, distinct 64-bit keys
     with payload (exact) and duplicate-heavy 32-bit keys (keys exact)."""
-    names = ("rss_k_small", "rss_k_mid", "rss_k_large")
-    caps = (16, 32, 64)
-    old = [ss.get_tuning(n) for n in names]
-    try:
-        for n, cap in zip(names, caps):
-            ss.set_tuning(n, min(k, cap))
+    from helpers import tuned
+    with tuned(rss_k_small=min(k, 16), rss_k_mid=min(k, 32), rss_k_large=min(k, 64)):
         sizes = np.random.default_rng(k).integers(17, 257, size=3000)
         off = inputs.offsets_from_sizes(sizes)
         total = int(off[-1])
@@ -213,9 +209,6 @@ def test_first_level_bucket_counts_with_payload(k, mode):
         wk, _ = oracle.sort_segments(dup, off)
         assert (gk == wk).all(), first_mismatch(gk, wk)
         assert ss.device_status() == 0
-    finally:
-        for n, v in zip(names, old):
-            ss.set_tuning(n, v)
 
 
 @pytest.mark.parametrize("mode", [ss.MODE_AUTO, ss.MODE_PERSISTENT], ids=["graph", "persistent"])
@@ -387,4 +380,34 @@ def test_insertion_sort_above_16_segmented(mode):
         got, _ = run_seg(k32, off, mode=mode)
         want, _ = oracle.sort_segments(k32, off)
         assert (got == want).all(), first_mismatch(got, want)
+        assert ss.device_status() == 0
+
+
+MAPPINGS = [dict(rss_bound_small=16, rss_bound_mid=64), dict(rss_bound_small=32, rss_bound_mid=96),
+            dict(rss_bound_small=48, rss_bound_mid=128), dict(rss_bound_small=64, rss_bound_mid=64),
+            dict(rss_oversample=1), dict(rss_oversample=4)]
+
+
+@pytest.mark.parametrize("knobs", MAPPINGS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()))
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_lane_group_mappings_and_oversampling(knobs, mode):
+    """The tuned wave-to-segment mapping (which RSS lane group takes which sizes)
+    and the oversampling of the 4-bucket levels, in every segmented form:
+    distinct 64-bit keys with payload and duplicate-heavy 32-bit keys."""
+    from helpers import tuned
+    rng = np.random.default_rng(91)
+    sizes = np.concatenate([np.arange(0, 257), rng.integers(17, 129, size=3000), rng.integers(0, 257, size=2000)])
+    rng.shuffle(sizes)
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    with tuned(**knobs):
+        keys = inputs.distinct_u64(total, seed=92)
+        vals = inputs.segment_index_payload(off)
+        gk, gv = run_seg(keys, off, vals, mode=mode)
+        wk, wv = oracle.sort_segments(keys, off, vals)
+        assert (gk == wk).all() and (gv == wv).all()
+        dup = (inputs.random_keys(np.uint32, total, seed=93) % 7).astype(np.uint32)
+        gk, _ = run_seg(dup, off, mode=mode)
+        wk, _ = oracle.sort_segments(dup, off)
+        assert (gk == wk).all(), first_mismatch(gk, wk)
         assert ss.device_status() == 0
