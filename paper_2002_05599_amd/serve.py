@@ -4,19 +4,25 @@ Clients submit sort jobs -- each a ragged batch of segments (keys + CSR
 offsets starting at 0) -- at any time.  A scheduler thread
 
   * admits jobs in arrival order while the device bytes of everything in
-    flight stay within an HBM budget (a job larger than the whole budget is
-    rejected at submission; the oldest waiting job blocks younger ones, so
-    no job starves);
+    flight stay within an HBM budget -- every copy the executor makes of a
+    job counts (a job larger than the whole budget is rejected at
+    submission; the oldest waiting job blocks younger ones, so no job
+    starves);
   * coalesces the admitted jobs into one device batch (keys concatenated,
     offsets rebased) as soon as an execution slot is free, so jobs arriving
     while others run are picked up by the next batch (continuous batching);
+    with a batching window, a batch that could still take more jobs waits up
+    to that long for them while another batch is running;
   * runs each batch on its own slot -- a HIP stream with its own pinned
     staging buffers -- as host-to-device copy, one ``segmented_sort`` call
     and device-to-host copy, so the copies and sorts of several batches
     overlap on the device (the library keeps separate working memory per
     stream);
   * completes each job when its batch's event has fired, recording latency
-    = completion time - arrival time on the host's monotonic clock.
+    = completion time - arrival time on the host's monotonic clock, where
+    the arrival time is the job's scheduled arrival when the client gives
+    one (an open-loop client that falls behind its schedule then shows the
+    delay in the latency instead of hiding it).
 
 Results are bit-identical whether a job runs alone or inside a mixed batch:
 segments are sorted independently and a batch only concatenates them.
@@ -54,6 +60,7 @@ class Job:
     done: threading.Event = field(default_factory=threading.Event)
 
     ready: object = None  # device jobs: event recorded on the submitting stream
+    queued: float = 0.0   # when submit() queued it (time.monotonic())
 
     @property
     def nkeys(self) -> int:
@@ -75,9 +82,10 @@ class Job:
         return self.result
 
 
-def device_bytes(nkeys: int, nseg: int, key_bytes: int) -> int:
-    """HBM a job occupies while in flight: its keys plus its offsets."""
-    return nkeys * key_bytes + (nseg + 1) * 4
+def device_bytes(nkeys: int, nseg: int, key_bytes: int, key_copies: int = 1) -> int:
+    """HBM a job occupies while in flight: key_copies copies of its keys plus
+    its offsets."""
+    return key_copies * nkeys * key_bytes + (nseg + 1) * 4
 
 
 def build_batch(jobs: List[Job]):
@@ -122,6 +130,13 @@ class GpuExecutor:
     @property
     def key_bytes(self) -> int:
         return self.dtype.itemsize
+
+    def admission_bytes(self, job) -> int:
+        """HBM the job holds while its batch runs: a host job's keys are
+        copied to the device once; a device job's keys are already resident
+        and the batch gathers them into a second copy."""
+        on_device = hasattr(job.keys, "is_cuda")
+        return device_bytes(job.nkeys, job.nseg, self.key_bytes, 2 if on_device else 1)
 
     def free_slot(self) -> Optional[int]:
         for i, b in enumerate(self.busy):
@@ -173,6 +188,43 @@ class GpuExecutor:
         self.busy[slot] = True
         self.inflight[slot] = (ev, dk, do, hout, starts)
 
+    def device_rate(self, pool, batch_jobs: int, reps: int = 3) -> float:
+        """Jobs per second the device sustains on ``pool`` (a list of (keys,
+        offsets) jobs, all on the device or all on the host) when it is
+        served in batches of ``batch_jobs`` consecutive jobs back to back on
+        one stream: the median over ``reps`` passes of HIP-event time, so the
+        figure does not depend on how fast the host thread schedules."""
+        torch = self._torch
+        stream = self.streams[0]
+        batches = [pool[i:i + batch_jobs] for i in range(0, len(pool), batch_jobs)]
+        staged = []
+        for b in batches:
+            jobs = [Job(-1, k, np.ascontiguousarray(o, dtype=np.int32)) for k, o in b]
+            starts = np.zeros(len(jobs) + 1, dtype=np.int64)
+            np.cumsum([j.nkeys for j in jobs], out=starts[1:])
+            parts = [j.offsets[:-1].astype(np.int64) - int(j.offsets[0]) + starts[i] for i, j in enumerate(jobs)]
+            parts.append(np.array([int(starts[-1])], dtype=np.int64))
+            off = torch.from_numpy(np.concatenate(parts).astype(np.int32)).pin_memory()
+            keys = [j.keys if hasattr(j.keys, "is_cuda") else torch.from_numpy(j.keys).pin_memory() for j in jobs]
+            staged.append((keys, off, int(starts[-1])))
+        times = []
+        for _ in range(reps):
+            with torch.cuda.stream(stream):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for keys, off, n in staged:
+                    do = off.to(self.device, non_blocking=True)
+                    dk = torch.cat([k.to(self.device, non_blocking=True) for k in keys]) if len(keys) > 1 \
+                        else keys[0].to(self.device, non_blocking=True).clone()
+                    self._ss.segmented_sort(dk, do, stream=stream)
+                    if not keys[0].is_cuda:
+                        dk.to("cpu", non_blocking=True)
+                e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        return len(pool) / float(np.median(times))
+
     def done(self, slot: int) -> bool:
         return self.inflight[slot][0].query()
 
@@ -190,12 +242,13 @@ class SortServer:
     """Admission + continuous batching over an executor (see module docstring)."""
 
     def __init__(self, executor, hbm_budget: int = 16 << 30, max_batch_keys: int = 64 << 20,
-                 max_batch_jobs: int = 256, poll_s: float = 20e-6):
+                 max_batch_jobs: int = 256, poll_s: float = 20e-6, batch_window_s: float = 0.0):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_batch_keys = int(max_batch_keys)
         self.max_batch_jobs = int(max_batch_jobs)
         self.poll_s = poll_s
+        self.batch_window_s = float(batch_window_s)
         self._lock = threading.Lock()
         self._cv = threading.Condition(self._lock)
         self._incoming = collections.deque()
@@ -212,9 +265,15 @@ class SortServer:
         self.max_concurrent_batches = 0
 
     # -- client side ----------------------------------------------------------
-    def submit(self, keys, offsets: np.ndarray) -> Job:
+    def _job_bytes(self, job) -> int:
+        f = getattr(self.ex, "admission_bytes", None)
+        return f(job) if f is not None else device_bytes(job.nkeys, job.nseg, self.ex.key_bytes)
+
+    def submit(self, keys, offsets: np.ndarray, arrival: Optional[float] = None) -> Job:
         """Queue a job: keys (numpy array, or a CUDA tensor already in HBM) and
-        host int32 CSR offsets.  Returns a Job to wait on."""
+        host int32 CSR offsets.  ``arrival``: the job's scheduled arrival on
+        time.monotonic()'s clock (default: now); latency is measured from it.
+        Returns a Job to wait on."""
         ready = None
         if hasattr(keys, "is_cuda") and keys.is_cuda:
             import torch
@@ -223,12 +282,14 @@ class SortServer:
         else:
             keys = np.ascontiguousarray(keys)
         offsets = np.ascontiguousarray(offsets, dtype=np.int32)
-        nkeys = int(keys.numel() if hasattr(keys, "numel") else keys.size)
-        need = device_bytes(nkeys, offsets.size - 1, self.ex.key_bytes)
+        now = time.monotonic()
+        job = Job(-1, keys, offsets, arrival=now if arrival is None else float(arrival), ready=ready)
+        need = self._job_bytes(job)
         if need > self.budget:
             raise AdmissionError(f"job needs {need} bytes of HBM, budget is {self.budget}")
+        job.queued = now
         with self._cv:
-            job = Job(self._next_jid, keys, offsets, arrival=time.monotonic(), ready=ready)
+            job.jid = self._next_jid
             self._next_jid += 1
             self._incoming.append(job)
             self._cv.notify()
@@ -259,7 +320,7 @@ class SortServer:
         jobs, nbytes, nkeys = [], 0, 0
         while self._pending and len(jobs) < self.max_batch_jobs:
             j = self._pending[0]
-            need = device_bytes(j.nkeys, j.nseg, self.ex.key_bytes)
+            need = self._job_bytes(j)
             if self._inflight_bytes + nbytes + need > self.budget:
                 break
             if jobs and nkeys + j.nkeys > self.max_batch_keys:
@@ -285,6 +346,8 @@ class SortServer:
             while self._pending:
                 slot = self.ex.free_slot()
                 if slot is None:
+                    break
+                if self._hold_for_window():
                     break
                 jobs, nbytes = self._admit_batch()
                 if not jobs:
@@ -332,6 +395,13 @@ class SortServer:
             if not progressed:
                 time.sleep(self.poll_s)
 
+    def _hold_for_window(self) -> bool:
+        """With a batching window: while another batch runs, a batch that could
+        take more jobs waits until its oldest job has queued for the window."""
+        if self.batch_window_s <= 0 or not self._inflight or len(self._pending) >= self.max_batch_jobs:
+            return False
+        return time.monotonic() - self._pending[0].queued < self.batch_window_s
+
     # -- reporting -------------------------------------------------------------
     def stats(self):
         lat = np.array([j.latency for j in self.completed if j.error is None])
@@ -359,7 +429,9 @@ def poisson_arrivals(n: int, rate_per_s: float, seed: int) -> np.ndarray:
 
 
 def run_open_loop(server: SortServer, jobs, arrivals: np.ndarray):
-    """Submit jobs[i % len(jobs)] at arrivals[i] (relative, seconds); wait for all."""
+    """Submit jobs[i % len(jobs)] at arrivals[i] (relative, seconds); wait for
+    all.  Each job's latency counts from its scheduled arrival, so time the
+    client spends behind schedule is part of it."""
     t0 = time.monotonic()
     handles = []
     for i, at in enumerate(arrivals):
@@ -367,7 +439,7 @@ def run_open_loop(server: SortServer, jobs, arrivals: np.ndarray):
         if delay > 0:
             time.sleep(delay)
         k, off = jobs[i % len(jobs)]
-        handles.append(server.submit(k, off))
+        handles.append(server.submit(k, off, arrival=t0 + at))
     for h in handles:
         h.wait(timeout=600)
     return handles

@@ -162,3 +162,60 @@ def test_concurrent_clients():
             h.wait(30)
     for i, (k, o) in enumerate(jobs):
         assert (out[i].result == oracle.sort_segments(k, o)[0]).all()
+
+
+def test_latency_counts_from_scheduled_arrival():
+    """A client that submits late (behind its schedule) sees that delay in the
+    job's latency: no coordinated omission."""
+    rng = np.random.default_rng(11)
+    ex = FakeExecutor(slots=2, service_s=0.001)
+    k, o = make_job(rng, 5)
+    with SortServer(ex) as srv:
+        sched = time.monotonic() - 0.050  # the job was due 50 ms ago
+        j = srv.submit(k, o, arrival=sched)
+        j.wait(10)
+    assert j.latency >= 0.050
+    assert j.arrival == sched and j.queued >= sched + 0.050
+
+
+def test_admission_counts_every_copy_the_executor_makes():
+    """An executor that keeps two copies of a job's keys is charged for both."""
+    rng = np.random.default_rng(12)
+    k, o = make_job(rng, 5)
+
+    class TwoCopies(FakeExecutor):
+        def admission_bytes(self, job):
+            return device_bytes(job.nkeys, job.nseg, self.key_bytes, 2)
+
+    one = device_bytes(k.size, o.size - 1, 4, 1)
+    two = device_bytes(k.size, o.size - 1, 4, 2)
+    assert two - one == 4 * k.size
+    ex = TwoCopies(slots=2, service_s=0.01)
+    with SortServer(ex, hbm_budget=two + one // 2) as srv:  # room for one job's two copies only
+        hs = [srv.submit(k, o) for _ in range(3)]
+        for h in hs:
+            h.wait(10)
+    assert srv.max_inflight_bytes <= two + one // 2
+    assert max(len(b) for b in srv.batches) == 1
+    with pytest.raises(AdmissionError):
+        SortServer(TwoCopies(), hbm_budget=two - 1).submit(k, o)
+
+
+def test_batching_window_coalesces_jobs():
+    """With a window, jobs that arrive while a batch runs wait for companions
+    and leave in fewer, larger batches."""
+    rng = np.random.default_rng(13)
+    pool = [make_job(rng, 5) for _ in range(4)]
+
+    def run(window):
+        ex = FakeExecutor(slots=2, service_s=0.004)
+        with SortServer(ex, max_batch_jobs=8, batch_window_s=window) as srv:
+            hs = []
+            for i in range(24):
+                hs.append(srv.submit(*pool[i % 4]))
+                time.sleep(0.0005)
+            for h in hs:
+                h.wait(10)
+        return srv.stats()["mean_jobs_per_batch"]
+
+    assert run(0.003) > run(0.0)
