@@ -43,6 +43,9 @@ template <int N, class K, int A = 1> struct TileLayout {
   static constexpr int P = (N % 2) ? N : N + 1;    // element pitch (element layout)
   static constexpr int kBytes = kVec ? TA * N * E : TA * P * E;
   static constexpr int kPerChunk = 16 / E;         // keys per 16-byte chunk
+  // odd N: the element layout (pitch N) is the tile's own byte order, so
+  // 16-byte chunks move between HBM and LDS whole
+  static constexpr bool kLinear = !kVec && P == N;
   // Rotation step: threads a and a' whose rows start in the same bank group
   // within one 8-thread pass get different rotations.
   static constexpr int kRotShift = (C == 2) ? 2 : (C == 4) ? 1 : (C == 6) ? 2 : 0;
@@ -111,6 +114,8 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
         if constexpr (L::kVec) {
           int a = g / L::C, k = g - (g / L::C) * L::C;
           *reinterpret_cast<u32x4*>(lds + L::chunk_slot(a, k) * 16) = buf[i];
+        } else if constexpr (L::kLinear) {
+          *reinterpret_cast<u32x4*>(lds + g * 16) = buf[i];
         } else {
           K parts[L::kPerChunk];
           __builtin_memcpy(parts, &buf[i], 16);
@@ -147,11 +152,9 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
 #pragma unroll
         for (int j = 0; j < N; ++j) r[j] = lds_ld<K>(lds + L::elem_offset(a, j));
       }
-#pragma unroll
-      for (int j = 0; j < N; ++j) r[j] = flip.enc(r[j]);
+      flip.enc_all(r);
       net_sort<F, N>(r);
-#pragma unroll
-      for (int j = 0; j < N; ++j) r[j] = flip.dec(r[j]);
+      flip.dec_all(r);
       if constexpr (L::kVec) {
 #pragma unroll
         for (int k = 0; k < L::C; ++k) {
@@ -177,6 +180,8 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
         if constexpr (L::kVec) {
           int a = g / L::C, k = g - (g / L::C) * L::C;
           v = *reinterpret_cast<const u32x4*>(lds + L::chunk_slot(a, k) * 16);
+        } else if constexpr (L::kLinear) {
+          v = *reinterpret_cast<const u32x4*>(lds + g * 16);
         } else {
           K parts[L::kPerChunk];
 #pragma unroll
@@ -195,6 +200,49 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
     for (int e = t; e < nelem; e += kTileThreads) {
       int a = e / N, j = e - (e / N) * N;
       gk[e] = lds_ld<K>(lds + L::elem_offset(a, j));
+    }
+  }
+}
+
+// Arrays of 8 bytes (uint32 n = 2): a 16-byte chunk holds two whole arrays,
+// so every thread loads its chunks straight from HBM (consecutive lanes,
+// consecutive chunks: fully coalesced), sorts them in registers and stores
+// them back; no LDS staging.  (For 16-byte arrays the staged tile measured
+// faster.)
+constexpr int kVecChunks = 4;  // chunks per thread in flight
+template <int F, int N, class K>
+__global__ void __launch_bounds__(kTileThreads)
+fixed_vec_kernel(K* __restrict__ keys, int64_t chunks, KeyMap<K> flip) {
+  constexpr int kArr = 16 / (N * (int)sizeof(K));  // arrays per chunk
+  static_assert(kArr * N * (int)sizeof(K) == 16, "one or two whole arrays per chunk");
+  const int64_t base = (int64_t)blockIdx.x * (kTileThreads * kVecChunks) + threadIdx.x;
+  u32x4* g4 = reinterpret_cast<u32x4*>(keys);
+  u32x4 buf[kVecChunks];
+#pragma unroll
+  for (int i = 0; i < kVecChunks; ++i) {
+    const int64_t c = base + (int64_t)i * kTileThreads;
+    if (c < chunks) buf[i] = __builtin_nontemporal_load(g4 + c);
+  }
+#pragma unroll
+  for (int i = 0; i < kVecChunks; ++i) {
+    const int64_t c = base + (int64_t)i * kTileThreads;
+    if (c < chunks) {
+      K r[kArr * N];
+      __builtin_memcpy(r, &buf[i], 16);
+#pragma unroll
+      for (int q = 0; q < kArr; ++q) {
+        K a[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = r[q * N + j];
+        flip.enc_all(a);
+        net_sort<F, N>(a);
+        flip.dec_all(a);
+#pragma unroll
+        for (int j = 0; j < N; ++j) r[q * N + j] = a[j];
+      }
+      u32x4 v;
+      __builtin_memcpy(&v, r, 16);
+      __builtin_nontemporal_store(v, g4 + c);
     }
   }
 }
@@ -229,6 +277,22 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<
   const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
+  if constexpr (N * sizeof(K) == 8) {
+    if (tiled) {
+      constexpr int64_t kArr = 16 / (N * sizeof(K));
+      const int64_t chunks = count / kArr;
+      const int64_t per = (int64_t)kTileThreads * kVecChunks;
+      const int64_t vblocks = (chunks + per - 1) / per;
+      if (vblocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+      if (chunks > 0)
+        hipLaunchKernelGGL((fixed_vec_kernel<F, N, K>), dim3((unsigned)vblocks), dim3(kTileThreads), 0, s, keys,
+                           chunks, flip);
+      if (chunks * kArr < count)  // an odd count of two-array chunks: the last array alone
+        hipLaunchKernelGGL((fixed_direct_kernel<F, N, K>), dim3(1), dim3(kTileThreads), 0, s,
+                           keys + chunks * kArr * N, (int64_t)1, (int64_t)N, flip);
+      return hipGetLastError();
+    }
+  }
   if (tiled) {
     // arrays per thread: the tuned value, or the largest smaller one whose tile fits
     if constexpr (tile_fits<N, K, 4>()) {

@@ -28,6 +28,29 @@ template <class K> struct KeyMap {
   __host__ __device__ __forceinline__ K enc(K x) const { return x ^ (flip | (top(x) & neg)); }
   // a word's top bit is clear exactly when its key was a negative float
   __host__ __device__ __forceinline__ K dec(K y) const { return y ^ (flip | (top(~y) & neg)); }
+
+  // The same maps over a whole register array, choosing the form once: the
+  // integer keys (neg == 0, a launch-wide value) take a single XOR per key.
+  template <int N>
+  __device__ __forceinline__ void enc_all(K (&r)[N]) const {
+    if (neg == 0) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] ^= flip;
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = enc(r[j]);
+    }
+  }
+  template <int N>
+  __device__ __forceinline__ void dec_all(K (&r)[N]) const {
+    if (neg == 0) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] ^= flip;
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) r[j] = dec(r[j]);
+    }
+  }
 };
 
 template <class K> constexpr KeyMap<K> kUnsignedMap{K(0), K(0)};
