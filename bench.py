@@ -63,7 +63,7 @@ def parse():
 
 # source files that define each profiled kernel's device code
 KERNEL_SOURCES = {
-    "fixed_tile_kernel<n=16,u32>": ("fixed.hip", "common.hpp", "networks_gen.hpp"),
+    "fixed_tile_kernel<n=16,u32>": ("fixed.hip", "common.hpp", "keymap.hpp", "networks_gen.hpp"),
 }
 
 

@@ -260,11 +260,11 @@ __device__ __forceinline__ K team_sort(K x, int t) {
 // per bucket, one key per lane, the T - NS spare lanes holding the maximum
 // key), sorted across the team; also clears the bucket's child counters and
 // records whether all of its k-1 splitters are equal.
-template <int KB, class K, int V, int G>
-__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np, int a4) {
-  // k = 4: the tuned oversampling (a team of 16 lanes holds up to 16 samples)
-  const int A = KB == 4 ? a4 : oversampling(KB);
-  const int NS = A * KB;
+template <int KB, int A4, class K, int V, int G>
+__device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
+  // k = 4: the tuned oversampling A4 (a team of 16 lanes holds up to 16 samples)
+  constexpr int A = KB == 4 ? A4 : oversampling(KB);
+  constexpr int NS = A * KB;
   constexpr int T = oversampling(KB) * KB <= 16 ? 16 : oversampling(KB) * KB;  // team size, a power of two
   constexpr int PER = G / T;              // buckets sampled per pass
   constexpr int kSpan = KB > 16 ? KB : 16;
@@ -294,8 +294,8 @@ __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int 
 // #{i = 1..k-1 : s_i < e} for the splitters s_i = smp[A*i - 1] of a sorted
 // sample held in LDS: a branch-free binary search (the in-memory splitter
 // tree of super scalar sample sort that the paper's register tree replaces).
-template <int LOGK, class K>
-__device__ __forceinline__ int lds_bucket(K e, const K* smp, int A) {
+template <int LOGK, int A, class K>
+__device__ __forceinline__ int lds_bucket(K e, const K* smp) {
   int j = 0;
 #pragma unroll
   for (int step = (1 << LOGK) / 2; step >= 1; step >>= 1) {
@@ -324,11 +324,10 @@ __device__ __forceinline__ int three_way(K e, K v) {
 // offsets, the children are registered (finish list or next-level pending
 // list, in position order) and every key is written to bucket start + child
 // offset + rank, together with its next-level bucket id.
-template <int LOGK, bool kFirst, class K, int V, int G>
-__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn,
-                                            int a4) {
+template <int LOGK, bool kFirst, int A4, class K, int V, int G>
+__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
   constexpr int k = 1 << LOGK;
-  const int a = k == 4 ? a4 : oversampling(k);
+  constexpr int a = k == 4 ? A4 : oversampling(k);
   constexpr int kSpan = k > 16 ? k : 16;  // entries per bucket in cnt/nextpb
   static_assert(kFirst || k <= 16, "only the first level has more than 16 children");
   static_assert(kSpan <= G, "the children of a bucket are scanned in one pass");
@@ -374,12 +373,12 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], spl[0]);
     } else if constexpr (kFirst) {
       const K* smp = &L.sample[0];
-      cc = lds_bucket<LOGK>(e[s], smp, a);
+      cc = lds_bucket<LOGK, a>(e[s], smp);
       if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], smp[a - 1]);
     } else {
       const int q = ok ? pp : 0;
       const K* smp = &L.sample[q * 16];
-      cc = lds_bucket<LOGK>(e[s], smp, a);
+      cc = lds_bucket<LOGK, a>(e[s], smp);
       const bool dg = L.deg[q] != 0;
       if (ballot(dg) != 0ull && dg) cc = three_way(e[s], smp[a - 1]);
     }
@@ -444,6 +443,24 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     }
   }
   wave_lds_sync();
+}
+
+// One level with k = 4 buckets and the tuned oversampling a4 (each a
+// compile-time variant: a run-time factor costs registers in every level).
+template <int A4, bool kFirst, class K, int V, int G>
+__device__ __forceinline__ void level_k4_a(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
+  sample_phase<4, A4>(L, cur, np);
+  wave_lds_sync();
+  split_level<2, kFirst, A4>(L, m, cur, np, nf, npn);
+}
+template <bool kFirst, class K, int V, int G>
+__device__ __forceinline__ void level_k4(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn, int a4) {
+  switch (a4) {
+    case 1: level_k4_a<1, kFirst>(L, m, cur, np, nf, npn); break;
+    case 2: level_k4_a<2, kFirst>(L, m, cur, np, nf, npn); break;
+    case 4: level_k4_a<4, kFirst>(L, m, cur, np, nf, npn); break;
+    default: level_k4_a<3, kFirst>(L, m, cur, np, nf, npn); break;
+  }
 }
 
 // Rank-counting sort of the remaining pending buckets (after kLevelCap levels).
@@ -516,32 +533,28 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
     int npn = 0;
     if (kk == 64) {
       if constexpr (max_first_k(G) >= 64) {
-        sample_phase<64>(L, cur, np, cfg.a4);
+        sample_phase<64, 3>(L, cur, np);
         wave_lds_sync();
-        split_level<6, true>(L, m, cur, np, nf, npn, cfg.a4);
+        split_level<6, true, 3>(L, m, cur, np, nf, npn);
       }
     } else if (kk == 32) {
       if constexpr (max_first_k(G) >= 32) {
-        sample_phase<32>(L, cur, np, cfg.a4);
+        sample_phase<32, 3>(L, cur, np);
         wave_lds_sync();
-        split_level<5, true>(L, m, cur, np, nf, npn, cfg.a4);
+        split_level<5, true, 3>(L, m, cur, np, nf, npn);
       }
     } else if (kk == 16) {
-      sample_phase<16>(L, cur, np, cfg.a4);
+      sample_phase<16, 3>(L, cur, np);
       wave_lds_sync();
-      split_level<4, true>(L, m, cur, np, nf, npn, cfg.a4);
+      split_level<4, true, 3>(L, m, cur, np, nf, npn);
     } else if (kk == 8) {
-      sample_phase<8>(L, cur, np, cfg.a4);
+      sample_phase<8, 3>(L, cur, np);
       wave_lds_sync();
-      split_level<3, true>(L, m, cur, np, nf, npn, cfg.a4);
+      split_level<3, true, 3>(L, m, cur, np, nf, npn);
     } else if (level == 0) {
-      sample_phase<4>(L, cur, np, cfg.a4);
-      wave_lds_sync();
-      split_level<2, true>(L, m, cur, np, nf, npn, cfg.a4);
+      level_k4<true>(L, m, cur, np, nf, npn, cfg.a4);
     } else {
-      sample_phase<4>(L, cur, np, cfg.a4);
-      wave_lds_sync();
-      split_level<2, false>(L, m, cur, np, nf, npn, cfg.a4);
+      level_k4<false>(L, m, cur, np, nf, npn, cfg.a4);
     }
     np = npn;
     cur ^= 1;

@@ -318,22 +318,6 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V
   }
 }
 
-// The IS+SN alternative for the RSS classes: the tile's segments sorted one
-// per lane by insertion sort in global memory (64 segments per pass).
-template <class K, int V>
-__device__ __forceinline__ void is_tile(K* keys, Pay<V>* vals, const int32_t* __restrict__ offsets,
-                                        const int32_t* __restrict__ ids, int list, int count, int first, int ntile,
-                                        KeyMap<K> flip) {
-  for (int j0 = 0; j0 < ntile; j0 += kWave) {
-    const int j = first + j0 + lane_id();
-    if (j0 + lane_id() < ntile && j < count) {
-      const int seg = ids[list + j];
-      const int lo = offsets[seg];
-      insertion_sort_global<K, V>(keys + lo, V ? vals + lo : nullptr, offsets[seg + 1] - lo, flip);
-    }
-  }
-}
-
 struct SortArgs {
   const int32_t* offsets;
   const int32_t* ids;
@@ -377,12 +361,6 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, Pay<V
         net_tile_mixed<F, K, V>(keys, vals, a.offsets, a.ids, list, count, first, flip);
       else
         net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
-      return;
-    }
-  }
-  if constexpr (KS == kKindAll || !is_net_kind(KS)) {
-    if (a.large_sort && c >= kNetClasses) {
-      is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, first, class_tile(c, rounds), flip);
       return;
     }
   }
@@ -506,11 +484,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
     const int list = (int)a.ctrl[kCtrlStart + kClass];
     const int k0 = a.k0[KS - kKindRss16];
     auto run_units = [&](int u, int n) {
-      if (a.large_sort)
-        is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, u * kGroups, n * kGroups, flip);
-      else
-        rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0,
-                             a.cfg);
+      rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0, a.cfg);
     };
     const int units = (count + kGroups - 1) / kGroups;
     const int R = class_rounds(kClass, count, a.rounds, waves, kPersistTpw);
@@ -611,8 +585,6 @@ seg_class_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, Ke
   const int first = tile * class_tile(c, rounds);
   if constexpr (KIND == 0) {
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
-  } else if (a.large_sort) {
-    is_tile<K, V>(keys, vals, a.offsets, a.ids, list, count, first, class_tile(c, rounds), flip);
   } else if constexpr (KIND == 1) {
     rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
                           a.k0[0], a.cfg);
@@ -659,6 +631,24 @@ static int large_blocks(DeviceCtx* c) {
       nb <= 0)
     nb = 1;
   return nb * c->num_cus;
+}
+
+// The IS+SN alternative for every RSS class (large_sort = 1): one lane per
+// segment, insertion sort in global memory.  The three class lists are
+// consecutive in the segment-id list.  A kernel of its own, so that the
+// Register Sample Sort kernels carry none of its code or registers.
+template <class K, int V>
+__global__ void __launch_bounds__(kSortThreads)
+seg_is_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, uint32_t* ctrl, KeyMap<K> flip) {
+  (void)ctrl;
+  const int list = (int)a.ctrl[kCtrlStart + kNetClasses];
+  const int count = (int)(a.ctrl[kCtrlCount + kNetClasses] + a.ctrl[kCtrlCount + kNetClasses + 1] +
+                          a.ctrl[kCtrlCount + kNetClasses + 2]);
+  for (int j = blockIdx.x * kSortThreads + threadIdx.x; j < count; j += gridDim.x * kSortThreads) {
+    const int seg = a.ids[list + j];
+    const int lo = a.offsets[seg];
+    insertion_sort_global<K, V>(keys + lo, V ? vals + lo : nullptr, a.offsets[seg + 1] - lo, flip);
+  }
 }
 
 // --- host side ---------------------------------------------------------------
@@ -762,7 +752,9 @@ struct SegLaunch {
   int persist_blocks[kKinds];  // grid of the persistent kernel per kind set
   int large_grid;              // work-groups of the large-class kernel
 
-  int nnodes() const { return split ? 8 : 5; }
+  bool is_rss;  // large_sort: one insertion-sort kernel replaces the RSS kernels (split form only)
+
+  int nnodes() const { return split ? (is_rss ? 6 : 8) : 5; }
   // kind set of node i >= 3: network classes, then the RSS classes largest first
   int node_kind(int i) const {
     if (!split) return kKindAll;
@@ -837,6 +829,13 @@ struct SegLaunch {
           p.kernelParams = p_sort_large;
           break;
         }
+        if (is_rss && i == 4) {
+          p.func = (void*)seg_is_kernel<K, V>;
+          p.gridDim = dim3(persist_blocks[kKindNet]);
+          p.blockDim = dim3(kSortThreads);
+          p.kernelParams = p_sort;
+          break;
+        }
         const int ks = node_kind(i);
         p.func = kernel_of(ks);
         p.gridDim = dim3(persist_blocks[ks]);
@@ -893,6 +892,7 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
     const int tiles = (count + ts - 1) / ts;
     const int blocks = (tiles + kSortWaves - 1) / kSortWaves;
     const int list = (int)sc->host_ctrl[kCtrlStart + cls];
+    if (cls >= kNetClasses && L.is_rss) continue;  // the insertion-sort kernel below takes every RSS class
     if (cls < kNetClasses)
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 0>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
@@ -906,6 +906,13 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 3>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
   }
+  if (L.is_rss) {
+    const int nrss = (int)(sc->host_ctrl[kCtrlCount + 15] + sc->host_ctrl[kCtrlCount + 16] +
+                           sc->host_ctrl[kCtrlCount + 17]);
+    if (nrss > 0)
+      hipLaunchKernelGGL((seg_is_kernel<K, V>), dim3((nrss + kSortThreads - 1) / kSortThreads), dim3(kSortThreads), 0,
+                         s, L.keys, L.vals, L.args, L.ctrl, L.flip);
+  }
   const int nlarge = (int)sc->host_ctrl[kCtrlCount + kLargeClass];
   if (nlarge > 0) {
     hipKernelNodeParams p = L.node(L.nnodes() - 1);
@@ -918,7 +925,8 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
 
 template <int F, class K, int V>
 static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
-  const int key = ((((int)sizeof(K) * 16 + V) * 3 + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0);
+  const int key = (((((int)sizeof(K) * 16 + V) * 3 + F) * 2 + (L.split ? 1 : 0)) * 2 + (L.mix ? 1 : 0)) * 2 +
+                  (L.is_rss ? 1 : 0);
   GraphEntry* g = nullptr;
   for (GraphEntry& ge : sc->graphs)
     if (ge.key == key && std::equal(ge.persist_blocks, ge.persist_blocks + kKinds, L.persist_blocks)) g = &ge;
@@ -952,7 +960,9 @@ static hipError_t run_graph(SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream
 
 template <int F, class K, int V>
 static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
-  L.split = tuning(sizeof(K)).persist_split != 0;
+  // the insertion-sort alternative always runs in the split form
+  L.is_rss = tuning(sizeof(K)).large_sort != 0;
+  L.split = tuning(sizeof(K)).persist_split != 0 || L.is_rss;
   for (int& b : L.persist_blocks) b = 0;
   if (L.split) {
     L.persist_blocks[kKindNet] = persistent_blocks<F, K, V, kKindNet>(c);
