@@ -357,9 +357,8 @@ def bench_network_vs_insertion(args):
     count = 1 << 24
     gen = torch.Generator(device="cuda")
     gen.manual_seed(12)
-    fam0 = {w: ss.get_tuning(f"{w}.family") for w in ("u32", "u64")}
     rows = {}
-    try:
+    with ss.tuned(family=0):
         for dtype, kb in (("u32", 4), ("i64", 8)):
             for n in range(2, 17):
                 row = {}
@@ -378,9 +377,7 @@ def bench_network_vs_insertion(args):
                                  "insertion_ms": ms[2], "network_speedup": ms[2] / best_net}
                     del src, buf
                 rows[f"{dtype}_n{n}"] = row
-    finally:
-        for w, f in fam0.items():
-            ss.set_tuning(f"{w}.family", f)
+
     torch.cuda.empty_cache()
     # 17..256 keys: RSS (network base case), RSS with insertion-sort base case, IS+SN
     keys, off = inputs.config3(nseg=1 << 20, dist="uniform")
@@ -390,14 +387,8 @@ def bench_network_vs_insertion(args):
     large = {}
     for name, knobs in (("rss_network_base", {}), ("rss_insertion_base", {"family": 2}),
                         ("is_sn_hybrid", {"large_sort": 1})):
-        old = {k: ss.get_tuning(k) for k in knobs}
-        try:
-            for k, v in knobs.items():
-                ss.set_tuning(k, v)
+        with ss.tuned(**knobs):
             ms, _ = time_steps(lambda b: ss.segmented_sort(b[0], to), bufs, 3, 1)
-        finally:
-            for k, v in old.items():
-                ss.set_tuning(k, v)
         large[name] = {"ms": ms}
     for name in large:
         large[name]["speedup_of_rss_network_base"] = large[name]["ms"] / large["rss_network_base"]["ms"]

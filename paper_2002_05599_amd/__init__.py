@@ -18,7 +18,7 @@ __all__ = [
     "SmallSortError", "lib", "lib_path", "sort_small", "segmented_sort", "device_status",
     "set_tuning", "get_tuning", "load_tuning", "tuning_path", "version", "KEY_CODES",
     "MODE_AUTO", "MODE_PERSISTENT", "MODE_PLAIN", "stream_copy", "segmented_sort_noalloc",
-    "NOALLOC_MAX_SEGMENTS", "sort", "sort_workspace_bytes",
+    "NOALLOC_MAX_SEGMENTS", "sort", "sort_workspace_bytes", "tuned",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -271,6 +271,33 @@ def set_tuning(name: str, value: int):
 
 def get_tuning(name: str) -> int:
     return int(lib().ss_get_tuning_value(name.encode()))
+
+
+class tuned:
+    """Context manager: set tuning knobs for a block, then restore them (a
+    knob kept per key width is restored per width)."""
+
+    def __init__(self, **knobs):
+        self.knobs = knobs
+
+    def __enter__(self):
+        self.old = {}
+        for k in self.knobs:
+            names = (f"u32.{k}", f"u64.{k}") if get_tuning(f"u32.{k}") >= 0 else (k,)
+            for name in names:
+                self.old[name] = get_tuning(name)
+        for k, v in self.knobs.items():
+            set_tuning(k, v)
+        return self
+
+    def __exit__(self, *exc):
+        for _ in range(2):  # twice: a bound may only be valid once the other is back
+            for k, v in self.old.items():
+                try:
+                    set_tuning(k, v)
+                except SmallSortError:
+                    pass
+        return False
 
 
 def load_tuning(path: str):

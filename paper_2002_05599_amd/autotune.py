@@ -11,7 +11,7 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
                    thread; fixed arrays of 2..8 keys)
   rss_bound_small, rss_bound_mid
                    the wave-to-segment mapping: which segment sizes get 16, 32
-                   or 64 lanes (a CSR batch of 17..128 keys)
+                   or 64 lanes (CSR batches of 17..256, 17..64 and 65..128 keys)
   rss_k_small/mid/large
                    first-level bucket count of each lane-group class (a CSR
                    batch of sizes within the class)
@@ -142,8 +142,11 @@ class Workloads:
             self.cases[(w, "family")] = ([_fixed_case(w, n, (1 << 22) // d, n) for n in (4, 8, 12, 16)]
                                          + [_csr_case(w, (1 << 18) // d, 17, 256, 5)])
             self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8)]
-            self.cases[(w, "rss_bound_small")] = [_csr_case(w, (1 << 19) // d, 17, 128, 7)]
-            self.cases[(w, "rss_bound_mid")] = self.cases[(w, "rss_bound_small")]
+            # the mapping is tuned on the whole RSS range and on each group size's own range
+            bounds = [_csr_case(w, (1 << 19) // d, 17, 256, 7), _csr_case(w, (1 << 18) // d, 17, 64, 8),
+                      _csr_case(w, (1 << 18) // d, 65, 128, 10)]
+            self.cases[(w, "rss_bound_small")] = bounds
+            self.cases[(w, "rss_bound_mid")] = bounds
             self.cases[(w, "rss_k_small")] = [_csr_case(w, (1 << 18) // d, 17, 64, 64)]
             self.cases[(w, "rss_k_mid")] = [_csr_case(w, (1 << 18) // d, 65, 128, 128)]
             self.cases[(w, "rss_k_large")] = [_csr_case(w, (1 << 18) // d, 129, 256, 256)]
