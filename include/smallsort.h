@@ -211,7 +211,7 @@ const char *ss_strerror(ss_status status);
 
 /*
  * Tuning parameters (variant choices found by the autotuner).  The first
- * eight are kept per key width: "<name>" sets both widths, "u32.<name>" or
+ * nine are kept per key width: "<name>" sets both widths, "u32.<name>" or
  * "u64.<name>" one of them (32-bit keys: uint32, int32, float; 64-bit keys:
  * uint64, int64, double); getting "<name>" returns -2 when the widths differ.
  *   "family"       n <= 16: 0 = fewest-comparator networks, 1 = Bose-Nelson
@@ -228,6 +228,11 @@ const char *ss_strerror(ss_status status);
  *                  with 4 buckets (1..4, default 3: the paper's "332")
  *   "fixed_apt"    arrays per thread of the fixed-layout network kernels (1, 2
  *                  or 4; reduced where the tile would not fit 32 KiB of LDS)
+ *   "rss_finish"   how Register Sample Sort finishes its buckets of 2..16
+ *                  keys: 0 = one network per bucket (Section 3, default),
+ *                  1 = rank counting (each key counts the smaller keys of its
+ *                  bucket and moves once; cheaper where an exchange moves
+ *                  64-bit keys or payloads)
  *   "persist_occ"  work-groups per CU of the persistent grid (0 = as many as
  *                  fit, 1..16)
  *   "rss_rounds"   most rounds of lane groups per RSS tile in segmented sorts

@@ -16,6 +16,8 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
                    first-level bucket count of each lane-group class (a CSR
                    batch of sizes within the class)
   rss_oversample   oversampling a of the 4-bucket levels (the RSS batch)
+  rss_finish       RSS buckets finished by networks or by rank counting (the
+                   RSS batch)
 For every width together (the ragged 10^7-segment batch plus the 2^20-array
 RSS batch): rss_rounds, persist_split, net_mix, interleave, persist_occ.
 
@@ -46,7 +48,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 PER_WIDTH = ("family", "fixed_apt", "rss_bound_small", "rss_bound_mid", "rss_k_small", "rss_k_mid",
-             "rss_k_large", "rss_oversample")
+             "rss_k_large", "rss_oversample", "rss_finish")
 GLOBAL = ("rss_rounds", "persist_split", "net_mix", "interleave", "persist_occ")
 NOISE = 0.01
 
@@ -151,6 +153,7 @@ class Workloads:
             self.cases[(w, "rss_k_mid")] = [_csr_case(w, (1 << 18) // d, 65, 128, 128)]
             self.cases[(w, "rss_k_large")] = [_csr_case(w, (1 << 18) // d, 129, 256, 256)]
             self.cases[(w, "rss_oversample")] = [_csr_case(w, (1 << 19) // d, 17, 256, 9)]
+            self.cases[(w, "rss_finish")] = self.cases[(w, "rss_oversample")]
         # global knobs: the ragged batch (u64 + payload) and the RSS-only batch (int32)
         k, v, off = inputs.config4(nseg=10_000_000 // d, seed=44)
         to = torch.from_numpy(off).cuda()
@@ -176,7 +179,8 @@ class Workloads:
 def candidates(name):
     return {"family": [0, 1, 2], "fixed_apt": [1, 2, 4], "rss_bound_small": [16, 32, 48, 64],
             "rss_bound_mid": [64, 96, 128], "rss_k_small": [4, 8, 16], "rss_k_mid": [4, 8, 16, 32],
-            "rss_k_large": [4, 8, 16, 32, 64], "rss_oversample": [1, 2, 3, 4], "rss_rounds": [4, 8, 16, 32, 64],
+            "rss_k_large": [4, 8, 16, 32, 64], "rss_oversample": [1, 2, 3, 4], "rss_finish": [0, 1],
+            "rss_rounds": [4, 8, 16, 32, 64],
             "persist_split": [0, 1], "net_mix": [0, 1], "interleave": [0, 1], "persist_occ": [0, 1, 2, 3]}[name]
 
 

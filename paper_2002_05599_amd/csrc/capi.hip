@@ -193,6 +193,7 @@ static const std::vector<TuneEntry>& tune_table() {
       {"rss_bound_mid", &Tuning::rss_bound_mid, 16, 128, false, true},
       {"rss_oversample", &Tuning::rss_oversample, 1, 4, false, true},
       {"fixed_apt", &Tuning::fixed_apt, 1, 4, false, true},
+      {"rss_finish", &Tuning::rss_finish, 0, 1, false, true},
       {"persist_occ", &Tuning::persist_occ, 0, 16, false, false},
       {"rss_rounds", &Tuning::rss_rounds, 1, 64, false, false},
       {"interleave", &Tuning::interleave, 0, 1, false, false},

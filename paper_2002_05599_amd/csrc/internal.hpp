@@ -23,6 +23,7 @@ struct Tuning {
   int rss_bound_mid = 128;   // largest segment sorted by a 32-lane RSS group (bound_small..128)
   int rss_oversample = 3;    // oversampling a of the RSS levels with 4 buckets (1..4)
   int fixed_apt = 1;         // arrays per thread of the fixed-layout network kernels (1, 2, 4)
+  int rss_finish = 0;        // RSS buckets finished by 0 networks, 1 rank counting
 };
 // A consistent copy of the current settings for keys of key_bytes (4 or 8)
 // bytes: the variant choices are kept per key width.

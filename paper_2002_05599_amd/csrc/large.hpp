@@ -28,9 +28,9 @@ template <class K, int V> struct LargeLds {
   static constexpr size_t kKeyBytes = (size_t)kMaxLargeN * sizeof(K);
   static constexpr size_t kValBytes = V ? (size_t)kMaxLargeN * sizeof(Pay<V>) : 0;
   static constexpr size_t kBufBytes = kKeyBytes + kValBytes;
-  static constexpr size_t kBytes = 2 * kBufBytes;
-  static_assert((kLargeThreads / kWave) * sizeof(GroupLds<K, V, 64>) <= kBufBytes,
-                "the run sorts' state must fit the second buffer");
+  static constexpr size_t kGroupBytes = (kLargeThreads / kWave) * sizeof(GroupLds<K, V, 64>);
+  // the second buffer also holds the run sorts' state
+  static constexpr size_t kBytes = kBufBytes + (kGroupBytes > kBufBytes ? kGroupBytes : kBufBytes);
 };
 
 // Sorts the m (<= kMaxLargeN) keys at gk (and payloads at gv) with the whole

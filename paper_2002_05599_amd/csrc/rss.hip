@@ -56,7 +56,7 @@ static hipError_t launch_rss_g(K* keys, int n, int64_t count, int64_t stride, Ke
 template <int F, class K>
 static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
   const Tuning t = tuning(sizeof(K));
-  const RssCfg cfg{t.rss_level_cap, t.rss_oversample};
+  const RssCfg cfg{t.rss_level_cap, t.rss_oversample, t.rss_finish};
   // the same lane-group mapping as the segmented size classes
   if (n <= t.rss_bound_small) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], cfg, s);
   if (n <= t.rss_bound_mid) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], cfg, s);
@@ -104,7 +104,7 @@ static hipError_t launch_large_f(K* keys, int n, int64_t count, int64_t stride, 
   if (attr != hipSuccess) return attr;
   const int64_t blocks = count < (1 << 20) ? count : (1 << 20);
   hipLaunchKernelGGL((large_fixed_kernel<F, K>), dim3((unsigned)blocks), dim3(kLargeThreads), kLds, s, keys, n,
-                     count, stride, flip, t.rss_k[2], RssCfg{t.rss_level_cap, t.rss_oversample});
+                     count, stride, flip, t.rss_k[2], RssCfg{t.rss_level_cap, t.rss_oversample, t.rss_finish});
   return hipGetLastError();
 }
 

@@ -29,11 +29,14 @@
 //   5. buckets of 2..16 keys join the finish list, larger ones are pending
 //      for the next level (the paper recurses until buckets are at most 16).
 //
-// Buckets on the finish list are sorted one per lane: the bucket is loaded
-// into the channels 0..m-1 of a network of the smallest size covering every
-// bucket of the wave, channels m.. are filled with the maximum key, and the
-// strict compare-exchange never moves a padding channel (a channel >= m holds
-// the maximum, which no real key exceeds), so channels 0..m-1 end sorted.
+// Buckets on the finish list are sorted one per lane, by the network of the
+// smallest size N covering every bucket of the wave: the lane loads the N keys
+// from its bucket's start on.  Buckets lie in key order, so the keys past the
+// bucket (later buckets, then the maximum key filling the slack past the
+// array) are never smaller than the bucket's own; a compare-exchange between
+// a bucket channel and a later channel therefore never swaps (the one-sided
+// argument that lets a network of N channels sort fewer keys), channels
+// 0..m-1 end sorted, and only they are stored.
 //
 // Termination with duplicate keys (not covered by the paper): if all k-1
 // splitters of a bucket are equal to v, the bucket is split three ways,
@@ -53,35 +56,48 @@ namespace ss {
 constexpr int kLevelCap = 8;
 
 // Run-time choices of the recursion: levels before the rank-counting
-// fallback (1..kLevelCap) and the oversampling factor a of the levels with
-// k = 4 buckets (1..4: a sample of 4a keys, splitters at ranks a, 2a, 3a).
+// fallback (1..kLevelCap), the oversampling factor a of the levels with
+// k = 4 buckets (1..4: a sample of 4a keys, splitters at ranks a, 2a, 3a) and
+// how buckets are finished (0: networks, 1: rank counting, see
+// finish_by_rank).
 struct RssCfg {
   int level_cap;
   int a4;
+  int finish;
 };
 
 template <class K, int V, int G> struct GroupLds {
   static constexpr int kCap = 4 * G;          // keys per array handled by a G-lane group
   static constexpr int kMaxPend = kCap / 17;  // buckets with more than 16 keys
   static constexpr int kMaxFin = kCap / 2;    // buckets with 2..16 keys
-  // keys (and values) of the array, plus kPad slack entries so that a
-  // 16-wide window starting at any position stays inside the array; the last
-  // entry doubles as the sink for stores that fall outside a bucket
-  static constexpr int kPad = 17;
+  // keys (and values) of the array, plus kPad slack entries holding the
+  // maximum key, so that a 16-wide window starting at any bucket of 2 or more
+  // keys stays inside the array and reads nothing smaller than the bucket's
+  // keys; the last entry, beyond every window, is the sink of the finish
+  static constexpr int kPad = 16;
   K key[kCap + kPad];
   Pay<V> val[V ? kCap + kPad : 1];
   // Per pending bucket b, 16 entries from b*16: its sorted sample, the count
-  // (then offset) of each child and each child's pending index at the next
+  // (then start position) of each child and each child's pending index at the next
   // level (0xFF if none).  The first level has one bucket and may use up to
   // 64 entries (k = 32 or 64 children), which the arrays hold for G >= 32.
-  K sample[kMaxPend * 16];
-  uint32_t cnt[kMaxPend * 16];
+  // The rank-counting finish reuses their space for one counter per position.
+  union {
+    struct {
+      K sample[kMaxPend * 16];
+      uint32_t cnt[kMaxPend * 16];
+    };
+    uint32_t tie[kCap];
+  };
   uint8_t nextpb[kMaxPend * 16];
   uint8_t deg[kMaxPend];           // all splitters of the bucket equal
   uint8_t pb[kCap];                // pending bucket of each position, or 0xFF
+  uint8_t bst[kCap];               // rank-counting finish: start of each position's final bucket
   uint16_t pend_st[2][kMaxPend];
   uint16_t pend_sz[2][kMaxPend];
   uint16_t fin[kMaxFin];            // finish list: start | size << 9 (start < 512, size <= 16)
+  static_assert(sizeof(K) * kMaxPend * 16 + 4 * kMaxPend * 16 >= 4 * kCap, "the counters fit the union");
+  static_assert(kCap <= 256, "bucket starts are bytes");
 };
 
 __device__ __forceinline__ uint16_t fin_pack(int st, int sz) { return (uint16_t)(st | (sz << 9)); }
@@ -124,31 +140,35 @@ __device__ __forceinline__ int classify(K e, const K* spl) {
   return TreeDescent<LOGK, K>::run(e, spl, 0);
 }
 
-// Finish the buckets of the finish list with networks of N channels.  The
-// N-key window at the bucket start is read unconditionally (the arrays have
-// slack) and the channels beyond the bucket are replaced by the maximum key;
-// stores beyond the bucket go to the sink entry instead of being masked.
+// Finish the buckets of the finish list with networks of N channels: each
+// lane reads the N-key window at its bucket's start (the keys past the
+// bucket are never smaller, see above) and stores back only the bucket's own
+// n channels (the windows reach at most 14 entries past the array; the last
+// slack entry is the sink).  Insertion sort, which is not data-oblivious, pads its window
+// with the maximum key instead, so that it does no work past the bucket.
 template <int F, int N, class K, int V, int G>
 __device__ __forceinline__ void finish_buckets(GroupLds<K, V, G>& L, bool ok, int st, int sz) {
-  using Lds = GroupLds<K, V, G>;
   K r[N];
   Pay<V> v[N];
   const int n = ok ? sz : 0;
-  const K* kp = &L.key[st];
+  K* kp = &L.key[st];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const K x = kp[j];
-    r[j] = j < n ? x : KeyTraits<K>::kMax;
+    r[j] = (F != kFamilyInsertion || j < n) ? x : KeyTraits<K>::kMax;
   }
+  Pay<V>* vp = &L.val[V ? st : 0];
   if constexpr (V) {
-    const Pay<V>* vp = &L.val[st];
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = vp[j];
     net_sort<F, N>(r, v);
   } else {
     net_sort<F, N>(r);
   }
-  constexpr int kSink = Lds::kCap + Lds::kPad - 1;
+  // channels past the bucket are stored to a sink entry that no window reads
+  // (a select of the index keeps the stores unconditional, which the register
+  // allocation of the kernels needs)
+  constexpr int kSink = GroupLds<K, V, G>::kCap + GroupLds<K, V, G>::kPad - 1;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const int dst = j < n ? st + j : kSink;
@@ -175,6 +195,72 @@ __device__ __forceinline__ void finish_dispatch(GroupLds<K, V, G>& L, bool ok, i
     case 14: finish_buckets<F, 14>(L, ok, st, sz); break;
     case 15: finish_buckets<F, 15>(L, ok, st, sz); break;
     default: finish_buckets<F, 16>(L, ok, st, sz); break;
+  }
+}
+
+// Finish by rank counting (a tuning alternative to the networks): every key
+// counts the keys of its final bucket that are smaller than itself, scanning
+// N keys from the bucket's start (past the bucket no key is smaller, see
+// above), and equal keys take consecutive slots from a counter at their
+// common rank.  Each key (and payload) then moves once, where a network
+// moves it at every exchange that swaps; for 64-bit keys or payloads, whose
+// exchanges take several selects each, that is the cheaper finish.  Keys not
+// in a bucket of 2..16 (buckets of one key, runs of equal keys, buckets that
+// the fallback sorted) have a bucket start at which they count no smaller
+// key, and stay where they are (a run of equal keys permutes within itself).
+template <int N, class K, int V, int G>
+__device__ __forceinline__ void finish_by_rank(GroupLds<K, V, G>& L, int m) {
+  const int gl = lane_id() % G;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) L.tie[gl + G * s] = 0u;
+  wave_lds_sync();
+  K e[4];
+  Pay<V> v[4];
+  int dst[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int i = gl + G * s;
+    dst[s] = -1;
+    if (i < m) {
+      e[s] = L.key[i];
+      if constexpr (V) v[s] = L.val[i];
+      const int b = L.bst[i];
+      const K* w = &L.key[b];
+      int lt = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) lt += (w[j] < e[s]) ? 1 : 0;
+      dst[s] = b + lt + (int)atomicAdd(&L.tie[b + lt], 1u);
+    }
+  }
+  wave_lds_sync();  // every key was read before any is written
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (dst[s] >= 0) {
+      L.key[dst[s]] = e[s];
+      if constexpr (V) L.val[dst[s]] = v[s];
+    }
+  }
+  wave_lds_sync();
+}
+
+template <class K, int V, int G>
+__device__ __forceinline__ void finish_rank_dispatch(GroupLds<K, V, G>& L, int m, int nmax) {
+  switch (nmax) {
+    case 2: finish_by_rank<2>(L, m); break;
+    case 3: finish_by_rank<3>(L, m); break;
+    case 4: finish_by_rank<4>(L, m); break;
+    case 5: finish_by_rank<5>(L, m); break;
+    case 6: finish_by_rank<6>(L, m); break;
+    case 7: finish_by_rank<7>(L, m); break;
+    case 8: finish_by_rank<8>(L, m); break;
+    case 9: finish_by_rank<9>(L, m); break;
+    case 10: finish_by_rank<10>(L, m); break;
+    case 11: finish_by_rank<11>(L, m); break;
+    case 12: finish_by_rank<12>(L, m); break;
+    case 13: finish_by_rank<13>(L, m); break;
+    case 14: finish_by_rank<14>(L, m); break;
+    case 15: finish_by_rank<15>(L, m); break;
+    default: finish_by_rank<16>(L, m); break;
   }
 }
 
@@ -296,13 +382,29 @@ __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int 
 // tree of super scalar sample sort that the paper's register tree replaces).
 template <int LOGK, int A, class K>
 __device__ __forceinline__ int lds_bucket(K e, const K* smp) {
-  int j = 0;
+  const K* p = smp;  // smp + A*j: each probe is a fixed offset from it
 #pragma unroll
   for (int step = (1 << LOGK) / 2; step >= 1; step >>= 1) {
-    const K sp = smp[A * (j + step) - 1];
-    j += (sp < e) ? step : 0;
+    const K sp = p[A * step - 1];
+    p = (sp < e) ? p + A * step : p;
   }
-  return j;
+  return (int)(p - smp) / A;
+}
+
+// Inclusive sum of x over aligned segments of S lanes (S = 16, 32 or 64):
+// Hillis-Steele steps within each row of 16 lanes by row shifts (a lane with
+// no source adds 0), then the last lane of a row is broadcast to the next row
+// (S >= 32) and lane 31 to the upper half (S = 64), all as DPP operands.
+template <int S>
+__device__ __forceinline__ uint32_t segment_scan(uint32_t x) {
+  static_assert(S == 16 || S == 32 || S == 64, "segments are rows, row pairs or the wave");
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  if constexpr (S >= 32) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  if constexpr (S >= 64) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return x;
 }
 
 // Three-way split of a bucket whose splitters all equal v: {<v}, {==v}, {>v}.
@@ -321,11 +423,13 @@ __device__ __forceinline__ int three_way(K e, K v) {
 // child) from an LDS atomic counter cnt[b][c] (one ds_add_rtn per key; the
 // order of equal-child keys inside a bucket does not matter, because every
 // bucket is sorted afterwards).  Per bucket, the counts are scanned into child
-// offsets, the children are registered (finish list or next-level pending
-// list, in position order) and every key is written to bucket start + child
-// offset + rank, together with its next-level bucket id.
+// start positions, the children are registered (finish list or next-level
+// pending list, in position order) and every key is written to its child's
+// start + rank, together with its next-level bucket id when a next level
+// follows.
 template <int LOGK, bool kFirst, int A4, class K, int V, int G>
-__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
+__device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn,
+                                            bool track) {
   constexpr int k = 1 << LOGK;
   constexpr int a = k == 4 ? A4 : oversampling(k);
   constexpr int kSpan = k > 16 ? k : 16;  // entries per bucket in cnt/nextpb
@@ -335,7 +439,6 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
   const int gl = lane % G;
   const int gbase = lane - gl;
   const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << gbase);
-  const uint64_t below = (1ull << lane) - 1ull;
 
   // Level 0 with few, narrow splitters: s_1..s_{k-1} held in registers and
   // searched by the register tree (paper, Section 3).  Wider trees would take
@@ -353,38 +456,53 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
 
   // per slot: the key, its payload and where it goes -- the index of its
   // (bucket, child) entry << 16 | its rank among that child's keys, or ~0 if
-  // the key is not in a pending bucket
+  // the key is not in a pending bucket.  The slots are handled side by side
+  // (loads, then the searches, then the counters), so that the dependent LDS
+  // reads of the four searches overlap.
   K e[4];
   Pay<V> v[4];
   uint32_t dst[4];
+  int pp[4], cc[4];
+  bool dg[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int i = gl + G * s;
-    dst[s] = ~0u;
-    if (ballot(i < m) == 0ull) continue;  // no group has keys in this slot
-    int pp = 0xFF;
-    if (i < m) pp = kFirst ? (np > 0 ? 0 : 0xFF) : (int)L.pb[i];
-    const bool ok = pp != 0xFF;
+    pp[s] = 0xFF;
+    if (i < m) pp[s] = kFirst ? (np > 0 ? 0 : 0xFF) : (int)L.pb[i];
+    const bool ok = pp[s] != 0xFF;
     e[s] = ok ? L.key[i] : K(0);
     if constexpr (V) v[s] = ok ? L.val[i] : Pay<V>(0);
-    int cc;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
     if constexpr (kRegTree) {
-      cc = classify<LOGK>(e[s], spl);
-      if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], spl[0]);
+      cc[s] = classify<LOGK>(e[s], spl);
+      dg[s] = deg0;
     } else if constexpr (kFirst) {
-      const K* smp = &L.sample[0];
-      cc = lds_bucket<LOGK, a>(e[s], smp);
-      if (ballot(deg0) != 0ull && deg0) cc = three_way(e[s], smp[a - 1]);
+      cc[s] = lds_bucket<LOGK, a>(e[s], &L.sample[0]);
+      dg[s] = deg0;
     } else {
-      const int q = ok ? pp : 0;
-      const K* smp = &L.sample[q * 16];
-      cc = lds_bucket<LOGK, a>(e[s], smp);
-      const bool dg = L.deg[q] != 0;
-      if (ballot(dg) != 0ull && dg) cc = three_way(e[s], smp[a - 1]);
+      const int q = pp[s] != 0xFF ? pp[s] : 0;
+      cc[s] = lds_bucket<LOGK, a>(e[s], &L.sample[q * 16]);
+      dg[s] = L.deg[q] != 0;
     }
-    // rank among the keys of the same (bucket, child): an LDS atomic counter
-    const int ci = pp * kSpan + cc;
-    if (ok) dst[s] = ((uint32_t)ci << 16) | atomicAdd(&L.cnt[ci], 1u);
+  }
+  // buckets whose splitters are all equal split three ways (rare: one
+  // wave-uniform test)
+  if (ballot(dg[0] || dg[1] || dg[2] || dg[3]) != 0ull) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int q = pp[s] != 0xFF ? pp[s] : 0;
+      const K v0 = kRegTree ? spl[0] : L.sample[q * 16 + a - 1];
+      if (dg[s]) cc[s] = three_way(e[s], v0);
+    }
+  }
+  // rank among the keys of the same (bucket, child): an LDS atomic counter
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int ci = pp[s] * kSpan + cc[s];
+    dst[s] = ~0u;
+    if (pp[s] != 0xFF) dst[s] = ((uint32_t)ci << 16) | atomicAdd(&L.cnt[ci], 1u);
   }
   wave_lds_sync();
 
@@ -398,13 +516,7 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     const int nchq = okq ? (dg ? 3 : k) : 0;
     const bool own = cq < nchq;
     const uint32_t x = own ? L.cnt[q] : 0u;
-    uint32_t incl = x;
-#pragma unroll
-    for (int d = 1; d < kSpan; d <<= 1) {
-      const uint32_t y = read_lane(incl, cq >= d ? lane - d : lane);
-      if (cq >= d) incl += y;
-    }
-    const uint32_t off = incl - x;
+    const uint32_t off = segment_scan<kSpan>(x) - x;
     const int cst = okq ? (int)L.pend_st[cur][pq] + (int)off : 0;
     const int csz = (int)x;
     const bool eq = dg && cq == 1;
@@ -412,14 +524,14 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
     const bool is_pend = own && !eq && csz > 16;
     const uint64_t Fm = ballot(is_fin) & gmask;
     const uint64_t Pm = ballot(is_pend) & gmask;
-    if (own) L.cnt[q] = off;
+    if (own) L.cnt[q] = (uint32_t)cst;
     if (is_fin) {
-      const int idx = min(nf + (int)__popcll(Fm & below), GroupLds<K, V, G>::kMaxFin - 1);
+      const int idx = min(nf + (int)mbcnt(Fm), GroupLds<K, V, G>::kMaxFin - 1);
       L.fin[idx] = fin_pack(cst, csz);
     }
     int pidx = 0xFF;
     if (is_pend) {
-      pidx = min(npn + (int)__popcll(Pm & below), GroupLds<K, V, G>::kMaxPend - 1);
+      pidx = min(npn + (int)mbcnt(Pm), GroupLds<K, V, G>::kMaxPend - 1);
       L.pend_st[cur ^ 1][pidx] = (uint16_t)cst;
       L.pend_sz[cur ^ 1][pidx] = (uint16_t)csz;
     }
@@ -431,15 +543,19 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
   }
   wave_lds_sync();
 
-  // scatter in place (every key of the slots was read above)
+  // scatter in place (every key of the slots was read above); the next-level
+  // bucket ids are needed only if some group of the wave has a next level
+  const bool more = ballot(npn > 0) != 0ull;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     if (dst[s] != ~0u) {
       const int pc = (int)(dst[s] >> 16);
-      const int pos = (int)L.pend_st[cur][pc / kSpan] + (int)L.cnt[pc] + (int)(dst[s] & 0xFFFFu);
+      const int cst = (int)L.cnt[pc];
+      const int pos = cst + (int)(dst[s] & 0xFFFFu);
       L.key[pos] = e[s];
       if constexpr (V) L.val[pos] = v[s];
-      L.pb[pos] = L.nextpb[pc];
+      if (more) L.pb[pos] = L.nextpb[pc];
+      if (track) L.bst[pos] = (uint8_t)cst;
     }
   }
   wave_lds_sync();
@@ -448,24 +564,26 @@ __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur
 // One level with k = 4 buckets and the tuned oversampling a4 (each a
 // compile-time variant: a run-time factor costs registers in every level).
 template <int A4, bool kFirst, class K, int V, int G>
-__device__ __forceinline__ void level_k4_a(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn) {
+__device__ __forceinline__ void level_k4_a(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn,
+                                           bool track) {
   sample_phase<4, A4>(L, cur, np);
   wave_lds_sync();
-  split_level<2, kFirst, A4>(L, m, cur, np, nf, npn);
+  split_level<2, kFirst, A4>(L, m, cur, np, nf, npn, track);
 }
 template <bool kFirst, class K, int V, int G>
-__device__ __forceinline__ void level_k4(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn, int a4) {
+__device__ __forceinline__ void level_k4(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn, int a4,
+                                         bool track) {
   switch (a4) {
-    case 1: level_k4_a<1, kFirst>(L, m, cur, np, nf, npn); break;
-    case 2: level_k4_a<2, kFirst>(L, m, cur, np, nf, npn); break;
-    case 4: level_k4_a<4, kFirst>(L, m, cur, np, nf, npn); break;
-    default: level_k4_a<3, kFirst>(L, m, cur, np, nf, npn); break;
+    case 1: level_k4_a<1, kFirst>(L, m, cur, np, nf, npn, track); break;
+    case 2: level_k4_a<2, kFirst>(L, m, cur, np, nf, npn, track); break;
+    case 4: level_k4_a<4, kFirst>(L, m, cur, np, nf, npn, track); break;
+    default: level_k4_a<3, kFirst>(L, m, cur, np, nf, npn, track); break;
   }
 }
 
 // Rank-counting sort of the remaining pending buckets (after kLevelCap levels).
 template <class K, int V, int G>
-__device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur, int np) {
+__device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur, int np, bool track) {
   const int gl = lane_id() % G;
   for (int p = 0; ballot(p < np) != 0ull; ++p) {
     const bool active = p < np;
@@ -499,6 +617,7 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
       if (active && i < sz) {
         L.key[st + rank[s]] = e[s];
         if constexpr (V) L.val[st + rank[s]] = v[s];
+        if (track) L.bst[st + rank[s]] = (uint8_t)(st + rank[s]);  // in final place: a bucket of its own
       }
     }
     wave_lds_sync();
@@ -512,8 +631,11 @@ __device__ __forceinline__ void rank_sort_pending(GroupLds<K, V, G>& L, int cur,
 template <int F, class K, int V, int G>
 __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, int k0, RssCfg cfg) {
   const int gl = lane_id() % G;
+  const bool track = cfg.finish != 0;  // record each position's final bucket (rank-counting finish)
   int np = m > 16 ? 1 : 0;
   int nf = (m >= 2 && m <= 16) ? 1 : 0;
+  if (gl < GroupLds<K, V, G>::kPad) L.key[m + gl] = KeyTraits<K>::kMax;  // the slack past the array
+  if (track && gl < 16) L.bst[gl] = 0;  // an array of at most 16 keys is one bucket
   if (gl == 0) {
     if (np) {
       L.pend_st[0][0] = 0;
@@ -526,7 +648,7 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
   int cur = 0;
   for (int level = 0; ballot(np > 0) != 0ull; ++level) {
     if (level == cfg.level_cap) {
-      rank_sort_pending(L, cur, np);
+      rank_sort_pending(L, cur, np, track);
       break;
     }
     const int kk = level == 0 ? min(k0, max_first_k(G)) : 4;
@@ -535,31 +657,39 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
       if constexpr (max_first_k(G) >= 64) {
         sample_phase<64, 3>(L, cur, np);
         wave_lds_sync();
-        split_level<6, true, 3>(L, m, cur, np, nf, npn);
+        split_level<6, true, 3>(L, m, cur, np, nf, npn, track);
       }
     } else if (kk == 32) {
       if constexpr (max_first_k(G) >= 32) {
         sample_phase<32, 3>(L, cur, np);
         wave_lds_sync();
-        split_level<5, true, 3>(L, m, cur, np, nf, npn);
+        split_level<5, true, 3>(L, m, cur, np, nf, npn, track);
       }
     } else if (kk == 16) {
       sample_phase<16, 3>(L, cur, np);
       wave_lds_sync();
-      split_level<4, true, 3>(L, m, cur, np, nf, npn);
+      split_level<4, true, 3>(L, m, cur, np, nf, npn, track);
     } else if (kk == 8) {
       sample_phase<8, 3>(L, cur, np);
       wave_lds_sync();
-      split_level<3, true, 3>(L, m, cur, np, nf, npn);
+      split_level<3, true, 3>(L, m, cur, np, nf, npn, track);
     } else if (level == 0) {
-      level_k4<true>(L, m, cur, np, nf, npn, cfg.a4);
+      level_k4<true>(L, m, cur, np, nf, npn, cfg.a4, track);
     } else {
-      level_k4<false>(L, m, cur, np, nf, npn, cfg.a4);
+      level_k4<false>(L, m, cur, np, nf, npn, cfg.a4, track);
     }
     np = npn;
     cur ^= 1;
   }
 
+  if (track) {
+    // the largest bucket of the wave's finish lists bounds every window
+    int nmax = 0;
+    for (int b = gl; b < nf; b += G) nmax = max(nmax, (int)(L.fin[b] >> 9));
+    nmax = (int)wave_max((uint32_t)nmax);
+    if (nmax >= 2) finish_rank_dispatch(L, m, nmax);
+    return;
+  }
   // finish every bucket of 2..16 keys with a network, one bucket per lane
   for (int base = 0; ballot(base < nf) != 0ull; base += G) {
     const int b = base + gl;

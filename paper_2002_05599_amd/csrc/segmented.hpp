@@ -262,7 +262,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V
   const int g = lane / G;
   const int narr = rounds * kGroups;
   int meta_lo = 0, meta_m = 0;  // lane l: bounds of array a0 + l of the tile
-  auto bounds = [&](int r, int& lo, int& m) {
+  auto bounds = [&](int r, int& lo, int& m) __attribute__((always_inline)) {
     const int a0 = r * kGroups;
     if ((a0 & (kWave - 1)) == 0) {
       const int a = a0 + lane;
@@ -282,7 +282,7 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V
   const int gl = lane % G;
   K nk[4];
   Pay<V> nv[4];
-  auto fetch = [&](int lo, int m) {
+  auto fetch = [&](int lo, int m) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = gl + G * s;
@@ -483,7 +483,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
     const int count = (int)a.ctrl[kCtrlCount + kClass];
     const int list = (int)a.ctrl[kCtrlStart + kClass];
     const int k0 = a.k0[KS - kKindRss16];
-    auto run_units = [&](int u, int n) {
+    auto run_units = [&](int u, int n) __attribute__((always_inline)) {
       rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0, a.cfg);
     };
     const int units = (count + kGroups - 1) / kGroups;
@@ -533,7 +533,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
   // as they finish so that uneven tiles do not leave a tail.  (Claiming every
   // tile from one device-wide counter costs more: atomics on one line from all
   // XCDs serialise.)
-  auto process = [&](int t) {
+  auto process = [&](int t) __attribute__((always_inline)) {
     if constexpr (is_net_kind(KS)) {
       int c = 0, idx = 0;
 #pragma unroll
@@ -717,7 +717,7 @@ inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
   a.net_mix = t.net_mix;
   a.bound_small = t.rss_bound_small;
   a.bound_mid = t.rss_bound_mid;
-  a.cfg = RssCfg{t.rss_level_cap, t.rss_oversample};
+  a.cfg = RssCfg{t.rss_level_cap, t.rss_oversample, t.rss_finish};
   a.large_sort = t.large_sort;
   return a;
 }

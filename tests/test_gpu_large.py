@@ -99,7 +99,7 @@ def test_large_segments_other_knobs():
     keys = inputs.distinct_u64(total, seed=10)
     vals = inputs.segment_index_payload(off)
     wk, wv = oracle.sort_segments(keys, off, vals)
-    for knobs in ({"large_sort": 1}, {"family": 2}, {"rss_level_cap": 1}, {"rss_k_large": 4}):
+    for knobs in ({"large_sort": 1}, {"family": 2}, {"rss_level_cap": 1}, {"rss_k_large": 4}, {"rss_finish": 1}):
         with tuned(**knobs):
             for mode in (ss.MODE_AUTO, ss.MODE_PLAIN):
                 gk, gv = run_seg(keys, off, vals, mode=mode)

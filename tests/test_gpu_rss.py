@@ -90,7 +90,7 @@ TUNINGS = [("rss_k_small", 4), ("rss_k_small", 8), ("rss_k_small", 16),
            ("rss_k_large", 64), ("family", 0), ("family", 1), ("family", 2), ("large_sort", 1),
            ("rss_oversample", 1), ("rss_oversample", 2), ("rss_oversample", 4),
            ("rss_bound_small", 16), ("rss_bound_small", 32), ("rss_bound_small", 48),
-           ("rss_bound_mid", 96), ("rss_bound_mid", 64)]
+           ("rss_bound_mid", 96), ("rss_bound_mid", 64), ("rss_finish", 1)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t[0]}={t[1]}")
@@ -121,15 +121,17 @@ def test_rss_stride_and_repeat():
     assert (run_fixed(a, n, count, stride) == got).all()
 
 
+@pytest.mark.parametrize("finish", [0, 1])
 @pytest.mark.parametrize("cap", [1, 2])
 @pytest.mark.parametrize("kind", ["uniform", "zipf", "two_values", "max_heavy", "one_big_dup"])
-def test_rss_level_cap_fallback_fixed(cap, kind):
+def test_rss_level_cap_fallback_fixed(cap, kind, finish):
     """Register Sample Sort stopped after `cap` levels: every bucket still above
     16 keys goes through the rank-counting fallback.  With a first level of 4
     buckets, arrays of 65..256 keys always leave such buckets, so the fallback
-    runs on every array of those sizes."""
+    runs on every array of those sizes; with both bucket finishes (the
+    rank-counting finish must leave the fallback's buckets in place)."""
     from helpers import tuned
-    with tuned(rss_level_cap=cap, rss_k_small=4, rss_k_mid=4, rss_k_large=4):
+    with tuned(rss_level_cap=cap, rss_k_small=4, rss_k_mid=4, rss_k_large=4, rss_finish=finish):
         for dtype in (np.uint32, np.int64):
             for n in (17, 40, 64, 100, 128, 200, 256):
                 count = 37
@@ -142,9 +144,10 @@ def test_rss_level_cap_fallback_fixed(cap, kind):
                 assert (got == want).all(), (cap, kind, n, first_mismatch(got, want, n))
 
 
+@pytest.mark.parametrize("finish", [0, 1])
 @pytest.mark.parametrize("cap", [1, 2])
 @pytest.mark.parametrize("mode", [ss.MODE_AUTO, ss.MODE_PLAIN], ids=["graph", "plain"])
-def test_rss_level_cap_fallback_segmented_payload(cap, mode):
+def test_rss_level_cap_fallback_segmented_payload(cap, mode, finish):
     """The fallback carries payloads: distinct keys (payload exact) and
     duplicate-heavy keys (keys exact, payload a per-segment permutation), with
     both first-level widths (narrow forces the fallback, wide rarely needs it)."""
@@ -153,7 +156,7 @@ def test_rss_level_cap_fallback_segmented_payload(cap, mode):
     off = inputs.offsets_from_sizes(sizes)
     total = int(off[-1])
     for k in (4, 16):
-        with tuned(rss_level_cap=cap, rss_k_small=k, rss_k_mid=k, rss_k_large=k):
+        with tuned(rss_level_cap=cap, rss_k_small=k, rss_k_mid=k, rss_k_large=k, rss_finish=finish):
             keys = inputs.distinct_u64(total, seed=cap + k)
             vals = inputs.segment_index_payload(off)
             tk, tv, to = to_dev(keys), to_dev(vals), to_dev(off)

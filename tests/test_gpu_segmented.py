@@ -385,7 +385,8 @@ def test_insertion_sort_above_16_segmented(mode):
 
 MAPPINGS = [dict(rss_bound_small=16, rss_bound_mid=64), dict(rss_bound_small=32, rss_bound_mid=96),
             dict(rss_bound_small=48, rss_bound_mid=128), dict(rss_bound_small=64, rss_bound_mid=64),
-            dict(rss_oversample=1), dict(rss_oversample=4)]
+            dict(rss_oversample=1), dict(rss_oversample=4), dict(rss_finish=0), dict(rss_finish=1),
+            dict(rss_finish=1, rss_bound_small=16, rss_bound_mid=64)]
 
 
 @pytest.mark.parametrize("knobs", MAPPINGS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()))
