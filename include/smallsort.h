@@ -242,11 +242,13 @@ const char *ss_strerror(ss_status status);
  *                  per RSS size class (each with only its own code and
  *                  registers); 0: a single persistent kernel for every class
  *   "net_mix"      1: in the persistent forms, segments of 2..16 keys are
- *                  sorted in batch order, 64 per tile of mixed sizes, each
- *                  lane running the network of the tile's largest segment
- *                  (neighbouring segments share cache lines); 0: one class
- *                  per size, each with its exact network.  The plain form
- *                  always uses one class per size.
+ *                  sorted in batch order, 64 per tile of mixed sizes: the
+ *                  tile's keys are read and written as one run of consecutive
+ *                  elements through LDS (neighbouring segments share cache
+ *                  lines), each lane running the network of the tile's
+ *                  largest segment; 0: one class per size, each with its
+ *                  exact network, one segment per lane read in place.  The
+ *                  plain form always uses one class per size.
  *   "rss_level_cap" levels of Register Sample Sort (1..8, default 8) after
  *                  which a bucket still above 16 keys is finished by a
  *                  rank-counting sort (each key placed at the number of keys

@@ -14,9 +14,10 @@
 //            ids grouped by class; no contended atomics)
 //   sort     persistent kernels, by default one per kind: the network
 //            classes (one segment per lane, the network of exactly that size
-//            in registers, 64-segment tiles), then each RSS class (17..64 /
-//            65..128 / 129..256 keys: Register Sample Sort with 16-, 32- or
-//            64-lane groups, rss.hpp).  Work is split into 8 partitions, one
+//            in registers, 64-segment tiles; or, tuned, every network size in
+//            batch order, each tile staged through LDS as one run), then each
+//            RSS class (17..64 / 65..128 / 129..256 keys: Register Sample
+//            Sort with 16-, 32- or 64-lane groups, rss.hpp).  Work is split into 8 partitions, one
 //            per XCD (blockIdx mod 8), each with its own claim counter; waves
 //            take their share round-robin and claim the remainder in small
 //            pieces at the end, so they finish together.  A single kernel for
@@ -237,6 +238,123 @@ __device__ __forceinline__ void net_tile_mixed(K* keys, Pay<V>* vals, const int3
   }
 }
 
+// LDS of one wave for a staged tile of mixed network sizes: the tile's keys
+// (and payloads) as one run of at most 64 x 16 elements plus a sink entry, the
+// segment of each element, and each segment's start in memory and in the run.
+constexpr int kNetRun = kWave * kMaxNet;
+template <class K, int V> struct NetLds {
+  K key[kNetRun + 1];
+  Pay<V> val[V ? kNetRun + 1 : 1];
+  int32_t start[kWave];
+  int32_t pre[kWave];
+  uint8_t owner[kNetRun];
+};
+
+// A tile of 64 consecutive segments of 2..16 keys in batch order (the class-0
+// list when the binning mixes the network sizes), staged through LDS: the
+// wave reads the tile's segments as one run of elements -- element e of their
+// concatenation belongs to segment owner[e] -- so each load instruction covers
+// 64 consecutive elements of neighbouring segments instead of one element of
+// 64 segments; each lane then sorts its own segment from LDS with the network
+// of the tile's largest segment (channels past the segment hold the maximum
+// key) and the run is stored back the same way.
+template <int N, int F, class K, int V>
+__device__ __forceinline__ void net_sort_run(NetLds<K, V>& S, int pre, int n) {
+  K r[N];
+  Pay<V> v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = i < n ? S.key[pre + i] : KeyTraits<K>::kMax;
+  if constexpr (V) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = S.val[i < n ? pre + i : kNetRun];
+    net_sort<F, N>(r, v);
+  } else {
+    net_sort<F, N>(r);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int d = i < n ? pre + i : kNetRun;  // the sink
+    S.key[d] = r[i];
+    if constexpr (V) S.val[d] = v[i];
+  }
+}
+
+template <int F, class K, int V>
+__device__ __forceinline__ void net_tile_staged(unsigned char* wave_lds, K* keys, Pay<V>* vals,
+                                                const int32_t* __restrict__ offsets, const int32_t* __restrict__ ids,
+                                                int list, int count, int first, KeyMap<K> flip) {
+  auto& S = *reinterpret_cast<NetLds<K, V>*>(wave_lds);
+  const int lane = lane_id();
+  const int j = first + lane;
+  int lo = 0, n = 0;
+  if (j < count) {
+    const int seg = ids[list + j];
+    lo = offsets[seg];
+    n = offsets[seg + 1] - lo;
+  }
+  const int incl = (int)segment_scan<kWave>((uint32_t)n);
+  const int pre = incl - n;
+  const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+  const int nmax = (int)wave_max((uint32_t)n);
+  S.start[lane] = lo;
+  S.pre[lane] = pre;
+  for (int i = 0; i < n; ++i) S.owner[pre + i] = (uint8_t)lane;
+  wave_lds_sync();
+  // the run in: every element's load is issued before any is written to LDS
+  K x[kMaxNet];
+  Pay<V> y[kMaxNet];
+#pragma unroll
+  for (int t = 0; t < kMaxNet; ++t) {
+    const int e = lane + kWave * t;
+    if (e < total) {
+      const int o = S.owner[e];
+      const int a = S.start[o] + (e - S.pre[o]);
+      x[t] = keys[a];
+      if constexpr (V) y[t] = vals[a];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxNet; ++t) {
+    const int e = lane + kWave * t;
+    if (e < total) {
+      S.key[e] = flip.enc(x[t]);
+      if constexpr (V) S.val[e] = y[t];
+    }
+  }
+  wave_lds_sync();
+  switch (nmax) {
+    case 0: case 1: break;
+    case 2: net_sort_run<2, F>(S, pre, n); break;
+    case 3: net_sort_run<3, F>(S, pre, n); break;
+    case 4: net_sort_run<4, F>(S, pre, n); break;
+    case 5: net_sort_run<5, F>(S, pre, n); break;
+    case 6: net_sort_run<6, F>(S, pre, n); break;
+    case 7: net_sort_run<7, F>(S, pre, n); break;
+    case 8: net_sort_run<8, F>(S, pre, n); break;
+    case 9: net_sort_run<9, F>(S, pre, n); break;
+    case 10: net_sort_run<10, F>(S, pre, n); break;
+    case 11: net_sort_run<11, F>(S, pre, n); break;
+    case 12: net_sort_run<12, F>(S, pre, n); break;
+    case 13: net_sort_run<13, F>(S, pre, n); break;
+    case 14: net_sort_run<14, F>(S, pre, n); break;
+    case 15: net_sort_run<15, F>(S, pre, n); break;
+    default: net_sort_run<16, F>(S, pre, n); break;
+  }
+  wave_lds_sync();
+  // the run out
+#pragma unroll
+  for (int t = 0; t < kMaxNet; ++t) {
+    const int e = lane + kWave * t;
+    if (e < total) {
+      const int o = S.owner[e];
+      const int a = S.start[o] + (e - S.pre[o]);
+      keys[a] = flip.dec(S.key[e]);
+      if constexpr (V) vals[a] = S.val[e];
+    }
+  }
+  wave_lds_sync();
+}
+
 // Per-wave LDS big enough for any RSS group layout of this key type.
 template <class K, int V> struct WaveLds {
   static constexpr size_t kBytes16 = 4 * sizeof(GroupLds<K, V, 16>);
@@ -357,7 +475,9 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, Pay<V
   const int first = tile_in_class * class_tile(c, rounds);
   if constexpr (KS == kKindAll || is_net_kind(KS)) {
     if (c < kNetClasses) {
-      if (KS == kKindNetMix || (KS == kKindAll && a.net_mix))
+      if constexpr (KS == kKindNetMix)
+        net_tile_staged<F, K, V>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, flip);
+      else if (KS == kKindAll && a.net_mix)
         net_tile_mixed<F, K, V>(keys, vals, a.offsets, a.ids, list, count, first, flip);
       else
         net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
@@ -446,7 +566,8 @@ template <class K, int V, int KS> struct PersistWaves {
 };
 
 template <class K, int V, int KS> struct PersistLds {
-  static constexpr size_t kBytes = is_net_kind(KS)   ? 16
+  static constexpr size_t kBytes = KS == kKindNet    ? 16
+                                   : KS == kKindNetMix ? sizeof(NetLds<K, V>)
                                    : KS == kKindRss16 ? 4 * sizeof(GroupLds<K, V, 16>)
                                    : KS == kKindRss32 ? 2 * sizeof(GroupLds<K, V, 32>)
                                    : KS == kKindRss64 ? sizeof(GroupLds<K, V, 64>)
