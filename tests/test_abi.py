@@ -74,23 +74,26 @@ def test_argument_errors_need_no_device(lib):
 
 
 def test_tuning_roundtrip(lib, tmp_path):
-    old = ss.get_tuning("rss_k_small")
-    old_family = ss.get_tuning("family")
+    # per-width knobs may differ between the widths: save and restore each width
+    old = {w: ss.get_tuning(f"{w}.rss_k_small") for w in ("u32", "u64")}
+    old_family = {w: ss.get_tuning(f"{w}.family") for w in ("u32", "u64")}
     ss.set_tuning("rss_k_small", 8)
     assert ss.get_tuning("rss_k_small") == 8
     with pytest.raises(ss.SmallSortError):
         ss.set_tuning("rss_k_small", 5)
     with pytest.raises(ss.SmallSortError):
         ss.set_tuning("rss_k_small", 32)  # a 16-lane group takes at most 16 buckets
-    old_mid, old_large = ss.get_tuning("rss_k_mid"), ss.get_tuning("rss_k_large")
+    old_mid = {w: ss.get_tuning(f"{w}.rss_k_mid") for w in ("u32", "u64")}
+    old_large = {w: ss.get_tuning(f"{w}.rss_k_large") for w in ("u32", "u64")}
     ss.set_tuning("rss_k_mid", 32)
     ss.set_tuning("rss_k_large", 64)
     assert ss.get_tuning("rss_k_mid") == 32 and ss.get_tuning("rss_k_large") == 64
     for name, bad in (("rss_k_mid", 64), ("rss_k_large", 48), ("rss_k_large", 128), ("rss_k_large", 2)):
         with pytest.raises(ss.SmallSortError):
             ss.set_tuning(name, bad)
-    ss.set_tuning("rss_k_mid", old_mid)
-    ss.set_tuning("rss_k_large", old_large)
+    for w in ("u32", "u64"):
+        ss.set_tuning(f"{w}.rss_k_mid", old_mid[w])
+        ss.set_tuning(f"{w}.rss_k_large", old_large[w])
     with pytest.raises(ss.SmallSortError):
         ss.set_tuning("no_such_knob", 1)
     assert ss.get_tuning("no_such_knob") == -1
@@ -104,8 +107,9 @@ def test_tuning_roundtrip(lib, tmp_path):
     for name, bad in (("family", 3), ("large_sort", 2)):
         with pytest.raises(ss.SmallSortError):
             ss.set_tuning(name, bad)
-    ss.set_tuning("family", old_family)
-    ss.set_tuning("rss_k_small", old)
+    for w in ("u32", "u64"):
+        ss.set_tuning(f"{w}.family", old_family[w])
+        ss.set_tuning(f"{w}.rss_k_small", old[w])
     old_cap = ss.get_tuning("rss_level_cap")
     for bad in (0, 9):
         with pytest.raises(ss.SmallSortError):
