@@ -394,8 +394,14 @@ __device__ __forceinline__ void rss_tile(unsigned char* wave_lds, K* keys, Pay<V
       }
     }
     const int src = (a0 & (kWave - 1)) + g;
-    lo = (int)read_lane((uint32_t)meta_lo, src);
-    m = (int)read_lane((uint32_t)meta_m, src);
+    if constexpr (G == kWave) {
+      // one array per wave: its bounds are wave-uniform (scalar registers)
+      lo = __builtin_amdgcn_readlane(meta_lo, src);
+      m = __builtin_amdgcn_readlane(meta_m, src);
+    } else {
+      lo = (int)read_lane((uint32_t)meta_lo, src);
+      m = (int)read_lane((uint32_t)meta_m, src);
+    }
   };
   const int gl = lane % G;
   K nk[4];
