@@ -185,7 +185,7 @@ ss_status ss_sort(int32_t key_type, void *keys, void *vals, int32_t val_bytes, i
  * that forbid hipMalloc.  Same layout, ownership, results and device status
  * reporting as ss_segmented_sort with SS_MODE_PERSISTENT; it calls no
  * hipMalloc, hipFree or other allocating routine.  Its working memory is one
- * fixed array per device in the library's code object (64 MiB + 80 KiB, held
+ * fixed array per device in the library's code object (64 MiB + 88 KiB, held
  * until the process ends), looked up on the first call on each device.
  *   nseg: 0..SS_NOALLOC_MAX_SEGMENTS; a larger batch returns SS_ESCRATCH
  *         before anything is enqueued.
@@ -211,7 +211,7 @@ const char *ss_strerror(ss_status status);
 
 /*
  * Tuning parameters (variant choices found by the autotuner).  The first
- * nine are kept per key width: "<name>" sets both widths, "u32.<name>" or
+ * ten are kept per key width: "<name>" sets both widths, "u32.<name>" or
  * "u64.<name>" one of them (32-bit keys: uint32, int32, float; 64-bit keys:
  * uint64, int64, double); getting "<name>" returns -2 when the widths differ.
  *   "family"       n <= 16: 0 = fewest-comparator networks, 1 = Bose-Nelson
@@ -220,7 +220,9 @@ const char *ss_strerror(ss_status status);
  *                  Sample Sort level for arrays of the 16-lane class
  *   "rss_k_mid"    same for the 32-lane class (4, 8, 16 or 32)
  *   "rss_k_large"  same for the 64-lane class (4, 8, 16, 32 or 64)
- *   "rss_bound_small" arrays of 17..bound_small keys are sorted by 16 lanes
+ *   "rss_bound_tiny" arrays of 17..bound_tiny keys are sorted by 8 lanes
+ *                  (16..32; 16 = none)
+ *   "rss_bound_small" arrays of bound_tiny+1..bound_small keys by 16 lanes
  *                  (16..64, default 64; at most 4 keys per lane)
  *   "rss_bound_mid" arrays of bound_small+1..bound_mid keys by 32 lanes
  *                  (bound_small..128, default 128), larger ones by 64 lanes

@@ -286,12 +286,18 @@ class tuned:
             names = (f"u32.{k}", f"u64.{k}") if get_tuning(f"u32.{k}") >= 0 else (k,)
             for name in names:
                 self.old[name] = get_tuning(name)
+        for _ in range(2):  # ordered knobs (the lane-group bounds) may need another pass
+            for k, v in self.knobs.items():
+                try:
+                    set_tuning(k, v)
+                except SmallSortError:
+                    pass
         for k, v in self.knobs.items():
             set_tuning(k, v)
         return self
 
     def __exit__(self, *exc):
-        for _ in range(2):  # twice: a bound may only be valid once the other is back
+        for _ in range(3):  # a bound may only be valid once the others are back
             for k, v in self.old.items():
                 try:
                     set_tuning(k, v)

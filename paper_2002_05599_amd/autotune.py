@@ -9,9 +9,10 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
                    plus the RSS batches, whose buckets the networks finish)
   fixed_apt        arrays per thread of the fixed-layout kernels (items per
                    thread; fixed arrays of 2..8 keys)
-  rss_bound_small, rss_bound_mid
-                   the wave-to-segment mapping: which segment sizes get 16, 32
-                   or 64 lanes (CSR batches of 17..256, 17..64 and 65..128 keys)
+  rss_bound_tiny, rss_bound_small, rss_bound_mid
+                   the wave-to-segment mapping: which segment sizes get 8, 16,
+                   32 or 64 lanes (CSR batches of 17..256, 17..64 and 65..128
+                   keys, and a ragged batch of geometric sizes, mean 24)
   rss_k_small/mid/large
                    first-level bucket count of each lane-group class (a CSR
                    batch of sizes within the class)
@@ -47,7 +48,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-PER_WIDTH = ("family", "fixed_apt", "rss_bound_small", "rss_bound_mid", "rss_k_small", "rss_k_mid",
+PER_WIDTH = ("family", "fixed_apt", "rss_bound_tiny", "rss_bound_small", "rss_bound_mid", "rss_k_small", "rss_k_mid",
              "rss_k_large", "rss_oversample", "rss_finish")
 GLOBAL = ("rss_rounds", "persist_split", "net_mix", "interleave", "persist_occ")
 NOISE = 0.01
@@ -117,18 +118,21 @@ def _fixed_case(width, n, count, seed):
     return Case(f"{width} fixed n={n}", lambda b: sort_small(b[0], n), [a], 2 * a.numel() * a.element_size())
 
 
-def _csr_case(width, nseg, lo, hi, seed):
+def _csr_case(width, nseg, lo, hi, seed, sizes=None, what=None):
     import torch
     from . import inputs, segmented_sort
-    off = inputs.offsets_from_sizes(inputs.csr_sizes(nseg, lo, hi, seed=seed))
+    if sizes is None:
+        sizes = inputs.csr_sizes(nseg, lo, hi, seed=seed)
+    what = what or f"CSR {lo}..{hi}"
+    off = inputs.offsets_from_sizes(sizes)
     total = int(off[-1])
     to = torch.from_numpy(off).cuda()
     if width == "u32":
         k = torch.from_numpy(inputs.random_keys(np.uint32, total, seed=lo)).cuda()
-        return Case(f"u32 CSR {lo}..{hi}", lambda b: segmented_sort(b[0], to), [k], 8 * total + 4 * nseg)
+        return Case(f"u32 {what}", lambda b: segmented_sort(b[0], to), [k], 8 * total + 4 * nseg)
     k = torch.from_numpy(inputs.distinct_u64(total, seed=lo)).cuda()
     v = torch.from_numpy(inputs.segment_index_payload(off)).cuda()
-    return Case(f"u64+payload CSR {lo}..{hi}", lambda b: segmented_sort(b[0], to, b[1]), [k, v],
+    return Case(f"u64+payload {what}", lambda b: segmented_sort(b[0], to, b[1]), [k, v],
                 24 * total + 4 * nseg)
 
 
@@ -145,8 +149,11 @@ class Workloads:
                                          + [_csr_case(w, (1 << 18) // d, 17, 256, 5)])
             self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8)]
             # the mapping is tuned on the whole RSS range and on each group size's own range
+            nr = (1 << 21) // d
             bounds = [_csr_case(w, (1 << 19) // d, 17, 256, 7), _csr_case(w, (1 << 18) // d, 17, 64, 8),
-                      _csr_case(w, (1 << 18) // d, 65, 128, 10)]
+                      _csr_case(w, (1 << 18) // d, 65, 128, 10),
+                      _csr_case(w, nr, 1, 256, 11, sizes=inputs.geometric_sizes(nr, 11), what="ragged, mean 24")]
+            self.cases[(w, "rss_bound_tiny")] = bounds
             self.cases[(w, "rss_bound_small")] = bounds
             self.cases[(w, "rss_bound_mid")] = bounds
             self.cases[(w, "rss_k_small")] = [_csr_case(w, (1 << 18) // d, 17, 64, 64)]
@@ -177,7 +184,8 @@ class Workloads:
 
 
 def candidates(name):
-    return {"family": [0, 1, 2], "fixed_apt": [1, 2, 4], "rss_bound_small": [16, 32, 48, 64],
+    return {"family": [0, 1, 2], "fixed_apt": [1, 2, 4], "rss_bound_tiny": [16, 24, 32],
+            "rss_bound_small": [16, 32, 48, 64],
             "rss_bound_mid": [64, 96, 128], "rss_k_small": [4, 8, 16], "rss_k_mid": [4, 8, 16, 32],
             "rss_k_large": [4, 8, 16, 32, 64], "rss_oversample": [1, 2, 3, 4], "rss_finish": [0, 1],
             "rss_rounds": [4, 8, 16, 32, 64],

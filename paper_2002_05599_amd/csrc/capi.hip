@@ -189,6 +189,7 @@ static const std::vector<TuneEntry>& tune_table() {
       {"rss_k_small", nullptr, 4, 16, true, true},
       {"rss_k_mid", nullptr, 4, 32, true, true},
       {"rss_k_large", nullptr, 4, 64, true, true},
+      {"rss_bound_tiny", &Tuning::rss_bound_tiny, 16, 32, false, true},
       {"rss_bound_small", &Tuning::rss_bound_small, 16, 64, false, true},
       {"rss_bound_mid", &Tuning::rss_bound_mid, 16, 128, false, true},
       {"rss_oversample", &Tuning::rss_oversample, 1, 4, false, true},
@@ -232,9 +233,10 @@ static bool valid_value(const TuneEntry& e, int64_t value, const Tuning& t) {
   if (value < e.lo || value > e.hi) return false;
   if (e.pow2_k && (value & (value - 1)) != 0) return false;
   if (e.slot == &Tuning::fixed_apt && value == 3) return false;
-  // a 16-lane group holds at most 64 keys, a 32-lane group 128; bound_mid >= bound_small
+  // a G-lane group holds at most 4G keys; bound_tiny <= bound_small <= bound_mid
   if (e.slot == &Tuning::rss_bound_mid && value < t.rss_bound_small) return false;
-  if (e.slot == &Tuning::rss_bound_small && value > t.rss_bound_mid) return false;
+  if (e.slot == &Tuning::rss_bound_small && (value > t.rss_bound_mid || value < t.rss_bound_tiny)) return false;
+  if (e.slot == &Tuning::rss_bound_tiny && value > t.rss_bound_small) return false;
   return true;
 }
 

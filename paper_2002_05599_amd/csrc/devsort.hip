@@ -190,13 +190,13 @@ static DsPlan ds_plan(int64_t n) {
 // buckets above 4096 keys are sorted afterwards in the same memory: their
 // levels are smaller, since the plan grows with n.
 static size_t ds_level_bytes(int64_t n, size_t ksz) {
-  if (n <= kDsBaseN) return 16384 + 1024 * 19 * 4;  // one segment through the segmented path
+  if (n <= kDsBaseN) return 16384 + kSegHistBytes;  // one segment through the segmented path
   const DsPlan p = ds_plan(n);
   size_t b = ds_align((size_t)p.s * ksz);                                    // sample
   b += ds_align((size_t)p.nspl * ksz);                                       // splitters
   b += 3 * ds_align((size_t)(p.nb + 1) * 4);                                 // counts, offsets, cursors
   b += ds_align((size_t)(p.nb + 1) * 4) + 256;                               // big-bucket list + count
-  b += ds_align((size_t)p.nb * 4) + ds_align(8192) + ds_align(1024 * 19 * 4);  // segmented-sort buffers
+  b += ds_align((size_t)p.nb * 4) + ds_align(kSegCtrlBytes) + ds_align(kSegHistBytes);  // segmented-sort buffers
   b += ds_align((size_t)p.s * ksz) + ds_level_bytes(p.s, ksz);              // sorting the sample
   return b;
 }
@@ -256,8 +256,8 @@ static hipError_t ds_sort(DeviceCtx* c, K* keys, Pay<V>* vals, int64_t n, K* tmp
       auto* off = static_cast<int32_t*>(cv.take(8));
       SegBuffers b;
       b.ids = static_cast<int32_t*>(cv.take(256));
-      b.ctrl = static_cast<uint32_t*>(cv.take(8192));
-      b.blockhist = static_cast<uint32_t*>(cv.take(1024 * 19 * 4));
+      b.ctrl = static_cast<uint32_t*>(cv.take(kSegCtrlBytes));
+      b.blockhist = static_cast<uint32_t*>(cv.take(kSegHistBytes));
       if (!b.blockhist) return hipErrorInvalidValue;
       const int32_t host_off[2] = {0, (int32_t)n};
       hipError_t e = hipMemcpyAsync(off, host_off, sizeof host_off, hipMemcpyHostToDevice, s);
@@ -279,8 +279,8 @@ static hipError_t ds_sort(DeviceCtx* c, K* keys, Pay<V>* vals, int64_t n, K* tmp
   auto* nbig = static_cast<uint32_t*>(cv.take(256));
   SegBuffers b;
   b.ids = static_cast<int32_t*>(cv.take((size_t)p.nb * 4));
-  b.ctrl = static_cast<uint32_t*>(cv.take(8192));
-  b.blockhist = static_cast<uint32_t*>(cv.take(1024 * 19 * 4));
+  b.ctrl = static_cast<uint32_t*>(cv.take(kSegCtrlBytes));
+  b.blockhist = static_cast<uint32_t*>(cv.take(kSegHistBytes));
   b.quiet = true;
   auto* sample_tmp = static_cast<K*>(cv.take((size_t)p.s * sizeof(K)));
   if (!sample_tmp) return hipErrorInvalidValue;

@@ -23,6 +23,7 @@ struct Tuning {
   int rss_bound_mid = 128;   // largest segment sorted by a 32-lane RSS group (bound_small..128)
   int rss_oversample = 3;    // oversampling a of the RSS levels with 4 buckets (1..4)
   int fixed_apt = 1;         // arrays per thread of the fixed-layout network kernels (1, 2, 4)
+  int rss_bound_tiny = 16;   // largest segment sorted by an 8-lane RSS group (16 = none, ..32)
   int rss_finish = 0;        // RSS buckets finished by 0 networks, 1 rank counting
 };
 // A consistent copy of the current settings for keys of key_bytes (4 or 8)
@@ -75,10 +76,14 @@ struct DeviceCtx {
 // and the per-block class histogram of the binning.
 struct SegBuffers {
   int32_t* ids = nullptr;
-  uint32_t* ctrl = nullptr;
-  uint32_t* blockhist = nullptr;
+  uint32_t* ctrl = nullptr;    // kSegCtrlBytes
+  uint32_t* blockhist = nullptr;  // kSegHistBytes
   bool quiet = false;  // skip segments above 4096 keys without flagging them in the status word
 };
+// Sizes of the binning's control block and per-block class histogram (1024
+// blocks x 20 size classes).
+constexpr size_t kSegCtrlBytes = 8192;
+constexpr size_t kSegHistBytes = 1024 * 20 * 4;
 
 // Largest batch of the no-allocation segmented entry point (its segment-id
 // list lives in the fixed scratch array).

@@ -1,7 +1,7 @@
 // Register Sample Sort of many arrays of 17..256 keys in the fixed layout
 // (array i at keys[i*stride, i*stride+n)).  A 256-thread work-group holds four
 // waves; each wave sorts 64/G arrays at once, one per G-lane group, with
-// G = 16 for n <= 64, 32 for n <= 128 and 64 above (at most 4 keys per lane).
+// G = 8, 16, 32 or 64 by the tuned bounds (at most 4 keys per lane).
 #include "internal.hpp"
 #include "large.hpp"
 #include "rss.hpp"
@@ -58,6 +58,7 @@ static hipError_t launch_rss_f(K* keys, int n, int64_t count, int64_t stride, Ke
   const Tuning t = tuning(sizeof(K));
   const RssCfg cfg{t.rss_level_cap, t.rss_oversample, t.rss_finish};
   // the same lane-group mapping as the segmented size classes
+  if (n <= t.rss_bound_tiny) return launch_rss_g<F, K, 8>(keys, n, count, stride, flip, 8, cfg, s);
   if (n <= t.rss_bound_small) return launch_rss_g<F, K, 16>(keys, n, count, stride, flip, t.rss_k[0], cfg, s);
   if (n <= t.rss_bound_mid) return launch_rss_g<F, K, 32>(keys, n, count, stride, flip, t.rss_k[1], cfg, s);
   return launch_rss_g<F, K, 64>(keys, n, count, stride, flip, t.rss_k[2], cfg, s);

@@ -269,10 +269,28 @@ __device__ __forceinline__ void finish_rank_dispatch(GroupLds<K, V, G>& L, int m
 // parameters the paper found best on most machines ("332", Section 4.5).
 __host__ __device__ constexpr int oversampling(int k) { return k == 4 ? 3 : (k >= 16 ? 1 : 16 / k); }
 
+// The oversampling a G-lane group uses for k buckets (a4: the tuned factor of
+// the 4-bucket levels): an 8-lane group sorts its sample across its 8 lanes,
+// so a*k <= 8 there.
+__host__ __device__ constexpr int sample_a(int k, int a4, int G) {
+  const int a = k == 4 ? a4 : oversampling(k);
+  return (G < 16 && a * k > G) ? G / k : a;
+}
+
+// Sample team size for k buckets: a power of two holding the a*k samples,
+// 16 lanes or the whole group if that is smaller.
+__host__ __device__ constexpr int sample_team(int k, int G) {
+  return oversampling(k) * k <= 16 ? (G < 16 ? G : 16) : oversampling(k) * k;
+}
+
+// Entries per pending bucket in the child counters: one pass of the group's
+// lanes scans the children of a bucket.
+__host__ __device__ constexpr int child_span(int k, int G) { return G < 16 ? G : (k > 16 ? k : 16); }
+
 // Largest first-level bucket count a G-lane group supports: the first
 // level's children are scanned in one pass of the group's lanes, and their
 // per-bucket entries must fit the arrays above.
-__host__ __device__ constexpr int max_first_k(int G) { return G >= 64 ? 64 : (G >= 32 ? 32 : 16); }
+__host__ __device__ constexpr int max_first_k(int G) { return G >= 64 ? 64 : (G >= 32 ? 32 : (G >= 16 ? 16 : 8)); }
 
 // x of lane (lane ^ J), for a compile-time J: DPP for the quad and row
 // patterns, a ds_swizzle within 32 lanes otherwise, a lane permute only when
@@ -349,12 +367,12 @@ __device__ __forceinline__ K team_sort(K x, int t) {
 template <int KB, int A4, class K, int V, int G>
 __device__ __forceinline__ void sample_phase(GroupLds<K, V, G>& L, int cur, int np) {
   // k = 4: the tuned oversampling A4 (a team of 16 lanes holds up to 16 samples)
-  constexpr int A = KB == 4 ? A4 : oversampling(KB);
+  constexpr int A = sample_a(KB, A4, G);
   constexpr int NS = A * KB;
-  constexpr int T = oversampling(KB) * KB <= 16 ? 16 : oversampling(KB) * KB;  // team size, a power of two
+  constexpr int T = sample_team(KB, G);  // team size, a power of two
   constexpr int PER = G / T;              // buckets sampled per pass
-  constexpr int kSpan = KB > 16 ? KB : 16;
-  static_assert(PER >= 1 && T * PER == G, "team must divide the group");
+  constexpr int kSpan = child_span(KB, G);
+  static_assert(PER >= 1 && T * PER == G && NS <= T, "team must divide the group and hold the sample");
   const int lane = lane_id();
   const int gl = lane % G;
   const int team = gl / T;
@@ -391,13 +409,25 @@ __device__ __forceinline__ int lds_bucket(K e, const K* smp) {
   return (int)(p - smp) / A;
 }
 
-// Inclusive sum of x over aligned segments of S lanes (S = 16, 32 or 64):
+// Inclusive sum of x over aligned segments of S lanes (S = 8, 16, 32 or 64):
 // Hillis-Steele steps within each row of 16 lanes by row shifts (a lane with
 // no source adds 0), then the last lane of a row is broadcast to the next row
 // (S >= 32) and lane 31 to the upper half (S = 64), all as DPP operands.
 template <int S>
 __device__ __forceinline__ uint32_t segment_scan(uint32_t x) {
-  static_assert(S == 16 || S == 32 || S == 64, "segments are rows, row pairs or the wave");
+  static_assert(S == 8 || S == 16 || S == 32 || S == 64, "segments are half rows, rows, row pairs or the wave");
+  if constexpr (S == 8) {
+    // half rows: the shifts by 1 and 2 would cross from lane 7 of a row to
+    // lane 8, so those lanes drop the shifted value; the shift by 4 reaches
+    // only the upper four lanes of each half row (banks 1 and 3)
+    const int h = lane_id() & 7;
+    const uint32_t y1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+    x += h >= 1 ? y1 : 0u;
+    const uint32_t y2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+    x += h >= 2 ? y2 : 0u;
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xA, false);  // row_shr:4, banks 1, 3
+    return x;
+  }
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
@@ -431,8 +461,8 @@ template <int LOGK, bool kFirst, int A4, class K, int V, int G>
 __device__ __forceinline__ void split_level(GroupLds<K, V, G>& L, int m, int cur, int np, int& nf, int& npn,
                                             bool track) {
   constexpr int k = 1 << LOGK;
-  constexpr int a = k == 4 ? A4 : oversampling(k);
-  constexpr int kSpan = k > 16 ? k : 16;  // entries per bucket in cnt/nextpb
+  constexpr int a = sample_a(k, A4, G);
+  constexpr int kSpan = child_span(k, G);  // entries per bucket in cnt/nextpb
   static_assert(kFirst || k <= 16, "only the first level has more than 16 children");
   static_assert(kSpan <= G, "the children of a bucket are scanned in one pass");
   const int lane = lane_id();
@@ -634,8 +664,16 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
   const bool track = cfg.finish != 0;  // record each position's final bucket (rank-counting finish)
   int np = m > 16 ? 1 : 0;
   int nf = (m >= 2 && m <= 16) ? 1 : 0;
-  if (gl < GroupLds<K, V, G>::kPad) L.key[m + gl] = KeyTraits<K>::kMax;  // the slack past the array
-  if (track && gl < 16) L.bst[gl] = 0;  // an array of at most 16 keys is one bucket
+  // the slack past the array holds the maximum key; an array of at most 16
+  // keys is one bucket (its final-bucket starts are 0)
+#pragma unroll
+  for (int t = 0; t < GroupLds<K, V, G>::kPad; t += G)
+    if (t + gl < GroupLds<K, V, G>::kPad) L.key[m + t + gl] = KeyTraits<K>::kMax;
+  if (track) {
+#pragma unroll
+    for (int t = 0; t < 16; t += G)
+      if (t + gl < 16) L.bst[t + gl] = 0;
+  }
   if (gl == 0) {
     if (np) {
       L.pend_st[0][0] = 0;
@@ -666,9 +704,11 @@ __device__ __forceinline__ void rss_group_sort_lds(GroupLds<K, V, G>& L, int m, 
         split_level<5, true, 3>(L, m, cur, np, nf, npn, track);
       }
     } else if (kk == 16) {
-      sample_phase<16, 3>(L, cur, np);
-      wave_lds_sync();
-      split_level<4, true, 3>(L, m, cur, np, nf, npn, track);
+      if constexpr (max_first_k(G) >= 16) {
+        sample_phase<16, 3>(L, cur, np);
+        wave_lds_sync();
+        split_level<4, true, 3>(L, m, cur, np, nf, npn, track);
+      }
     } else if (kk == 8) {
       sample_phase<8, 3>(L, cur, np);
       wave_lds_sync();

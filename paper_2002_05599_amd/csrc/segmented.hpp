@@ -16,16 +16,18 @@
 //            classes (one segment per lane, the network of exactly that size
 //            in registers, 64-segment tiles; or, tuned, every network size in
 //            batch order, each tile staged through LDS as one run), then each
-//            RSS class (17..64 / 65..128 / 129..256 keys: Register Sample
-//            Sort with 16-, 32- or 64-lane groups, rss.hpp).  Work is split into 8 partitions, one
+//            RSS class (Register Sample Sort with 8-, 16-, 32- or 64-lane
+//            groups, rss.hpp).  Work is split into 8 partitions, one
 //            per XCD (blockIdx mod 8), each with its own claim counter; waves
 //            take their share round-robin and claim the remainder in small
 //            pieces at the end, so they finish together.  A single kernel for
 //            every class is kept as a tuning choice.
 //
-// Size classes: 0..14 = sizes 2..16, 15 = 17..64, 16 = 65..128, 17 = 129..256,
-// 18 = 257..4096 (one work-group per segment: Register Sample Sort of runs of
-// 256 keys, then merge rounds in LDS, large.hpp).  Sizes 0 and 1 need no work.
+// Size classes: 0..14 = sizes 2..16; 15..18 = the RSS classes of 8-, 16-,
+// 32- and 64-lane groups (17..bt, ..bs, ..bm, ..256 keys for the tuned bounds
+// bt <= bs <= bm; by default 17..32, 33..64, 65..128, 129..256); 19 =
+// 257..4096 (one work-group per segment: Register Sample Sort of runs of 256
+// keys, then merge rounds in LDS, large.hpp).  Sizes 0 and 1 need no work.
 // A segment longer than 4096 keys or with a negative size is skipped and
 // flagged in the status word.
 //
@@ -46,10 +48,15 @@
 
 namespace ss {
 
-constexpr int kClasses = 19;       // size classes of the binning
-constexpr int kTiledClasses = 18;  // classes sorted in wave-sized tiles (networks, RSS)
-constexpr int kLargeClass = 18;    // 257..4096 keys: one work-group per segment
+constexpr int kClasses = 20;       // size classes of the binning
+constexpr int kTiledClasses = 19;  // classes sorted in wave-sized tiles (networks, RSS)
+constexpr int kLargeClass = 19;    // 257..4096 keys: one work-group per segment
 constexpr int kNetClasses = 15;
+constexpr int kRssClasses = 4;     // 15..18: 8-, 16-, 32-, 64-lane groups
+
+// Lanes per array of RSS class c (15..18), and arrays per wave.
+__host__ __device__ constexpr int rss_group(int c) { return 8 << (c - kNetClasses); }
+__host__ __device__ constexpr int class_groups(int c) { return c < kNetClasses ? 1 : kWave / rss_group(c); }
 constexpr int kBinThreads = 256;
 constexpr int kBinItems = 4;                       // segments per thread per chunk
 constexpr int kBinChunk = kBinThreads * kBinItems;  // segments per block iteration
@@ -62,17 +69,20 @@ constexpr int kCtrlCount = 0;        // [kClasses] segments per class
 constexpr int kCtrlStart = 32;       // [kClasses] start of each class list
 constexpr int kCtrlTile = 128;       // tile counters: kind set k, partition p at kCtrlTile + (8k + p) * 32
 constexpr int kTileParts = 8;        // counter partitions (one 128-byte line each)
-constexpr int kCtrlWords = kCtrlTile + 6 * kTileParts * 32;  // 6 kind sets
+constexpr int kCtrlWords = kCtrlTile + 7 * kTileParts * 32;  // 7 kind sets
+static_assert(kCtrlWords * 4 <= (int)kSegCtrlBytes && kBinBlocks * kClasses * 4 == (int)kSegHistBytes,
+              "the binning's buffers have the sizes the other units assume");
 
-// bs, bm: the largest sizes given to 16- and 32-lane RSS groups (tuned:
-// bs in 16..64, bm in bs..128; a 16-lane group holds up to 64 keys, a 32-lane
-// group up to 128).
-__device__ __forceinline__ int size_class(int sz, int bs, int bm) {
+// bt, bs, bm: the largest sizes given to 8-, 16- and 32-lane RSS groups
+// (tuned: bt in 16..32, bs in bt..64, bm in bs..128; a G-lane group holds up
+// to 4G keys).
+__device__ __forceinline__ int size_class(int sz, int bt, int bs, int bm) {
   if (sz < 2) return sz >= 0 ? -1 : -3;  // -1: nothing to do, -3: bad offsets
   if (sz <= 16) return sz - 2;
-  if (sz <= bs) return 15;
-  if (sz <= bm) return 16;
-  if (sz <= kMaxN) return 17;
+  if (sz <= bt) return 15;
+  if (sz <= bs) return 16;
+  if (sz <= bm) return 17;
+  if (sz <= kMaxN) return 18;
   if (sz <= kMaxLargeN) return kLargeClass;
   return -2;  // too big
 }
@@ -87,8 +97,7 @@ constexpr int kPersistTpw = 4;
 constexpr int kPlainTpw = 8;
 __host__ __device__ __forceinline__ int class_rounds(int c, int count, int rounds, int waves, int tpw) {
   if (c < kNetClasses) return 1;
-  const int groups = c == 15 ? 4 : (c == 16 ? 2 : 1);
-  const int per = groups * waves * tpw;
+  const int per = class_groups(c) * waves * tpw;
   const int r = count / (per > 0 ? per : 1);
   return r < 1 ? 1 : (r > rounds ? rounds : r);
 }
@@ -96,13 +105,13 @@ __host__ __device__ __forceinline__ int class_rounds(int c, int count, int round
 // Tile size (segments) of a class; rounds = RSS group rounds per tile.
 __host__ __device__ __forceinline__ int class_tile(int c, int rounds) {
   if (c < kNetClasses) return kWave;
-  const int groups = c == 15 ? 4 : (c == 16 ? 2 : 1);
-  return groups * rounds;
+  return class_groups(c) * rounds;
 }
 
-// Classes in the order the persistent kernel hands out tiles.
+// Classes in the order the persistent kernel hands out tiles: the RSS
+// classes largest first, then the network classes.
 __host__ __device__ __forceinline__ int class_at(int order) {
-  return order < 3 ? 17 - order : 14 - (order - 3);
+  return order < kRssClasses ? kNetClasses + kRssClasses - 1 - order : kNetClasses - 1 - (order - kRssClasses);
 }
 
 // --- binning kernels (segmented_common.hip) -----------------------------------
@@ -116,12 +125,13 @@ __global__ void seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t 
 
 // The binning's parameters in one word: bit 0 = every network size goes to
 // class 0, whose segments are then sorted in batch order (see
-// net_tile_mixed); bits 8..15 and 16..23 = the RSS class bounds bs and bm.
-__host__ __device__ __forceinline__ int pack_bins(int mix, int bs, int bm) {
-  return (mix ? 1 : 0) | (bs << 8) | (bm << 16);
+// net_tile_staged); bits 8..15, 16..23 and 24..31 = the RSS class bounds bs,
+// bm and bt.
+__host__ __device__ __forceinline__ int pack_bins(int mix, int bt, int bs, int bm) {
+  return (mix ? 1 : 0) | (bs << 8) | (bm << 16) | (bt << 24);
 }
 __device__ __forceinline__ int bin_class(int sz, int bins) {
-  const int c = size_class(sz, (bins >> 8) & 0xFF, (bins >> 16) & 0xFF);
+  const int c = size_class(sz, (bins >> 24) & 0xFF, (bins >> 8) & 0xFF, (bins >> 16) & 0xFF);
   return ((bins & 1) && c > 0 && c < kNetClasses) ? 0 : c;
 }
 
@@ -357,11 +367,13 @@ __device__ __forceinline__ void net_tile_staged(unsigned char* wave_lds, K* keys
 
 // Per-wave LDS big enough for any RSS group layout of this key type.
 template <class K, int V> struct WaveLds {
+  static constexpr size_t kBytes8 = 8 * sizeof(GroupLds<K, V, 8>);
   static constexpr size_t kBytes16 = 4 * sizeof(GroupLds<K, V, 16>);
   static constexpr size_t kBytes32 = 2 * sizeof(GroupLds<K, V, 32>);
   static constexpr size_t kBytes64 = sizeof(GroupLds<K, V, 64>);
-  static constexpr size_t kBytes = kBytes16 > kBytes32 ? (kBytes16 > kBytes64 ? kBytes16 : kBytes64)
-                                                       : (kBytes32 > kBytes64 ? kBytes32 : kBytes64);
+  static constexpr size_t kBytesA = kBytes8 > kBytes16 ? kBytes8 : kBytes16;
+  static constexpr size_t kBytesB = kBytes32 > kBytes64 ? kBytes32 : kBytes64;
+  static constexpr size_t kBytes = kBytesA > kBytesB ? kBytesA : kBytesB;
 };
 
 // One tile: `rounds` rounds of kWave/G arrays (one per G-lane group).  The
@@ -448,28 +460,36 @@ struct SortArgs {
   const uint32_t* ctrl;
   int rounds;     // maximum RSS group rounds per tile
   int waves;      // resident waves of a per-class launch (plain baseline)
-  int k0[3];
+  int k0[kRssClasses];  // first-level bucket count per RSS class (15..18)
   int interleave;  // alternate RSS and network tiles in the persistent kernel
   int net_mix;     // class 0 holds every network size, in batch order
   RssCfg cfg;   // RSS levels before the rank-counting fallback
   int large_sort;  // 1: the RSS classes are sorted by insertion sort (IS+SN)
+  int bound_tiny;   // largest segment of the 8-lane RSS class (16: the class is empty)
   int bound_small;  // largest segment of the 16-lane RSS class
   int bound_mid;    // largest segment of the 32-lane RSS class
 };
 
 // Kind sets of the persistent kernels: every class (one kernel holding every
 // handler), the network classes (per size, or mixed sizes in batch order), or
-// one RSS class (17..64, 65..128, 129..256).
+// one RSS class (8-, 16-, 32- or 64-lane groups).
 constexpr int kKindAll = 0, kKindNet = 1, kKindRss16 = 2, kKindRss32 = 3, kKindRss64 = 4, kKindNetMix = 5,
-              kKinds = 6;
+              kKindRss8 = 6, kKinds = 7;
 static_assert(kCtrlTile + kKinds * kTileParts * 32 <= kCtrlWords, "claim counters must fit ctrl");
 
 __host__ __device__ constexpr bool is_net_kind(int ks) { return ks == kKindNet || ks == kKindNetMix; }
+__host__ __device__ constexpr bool is_rss_kind(int ks) {
+  return ks == kKindRss8 || ks == kKindRss16 || ks == kKindRss32 || ks == kKindRss64;
+}
+// The class of an RSS kind set, and its lanes per array.
+__host__ __device__ constexpr int rss_class_of(int ks) {
+  return ks == kKindRss8 ? kNetClasses : kNetClasses + 1 + (ks - kKindRss16);
+}
 
 __host__ __device__ __forceinline__ bool in_kind(int c, int ks) {
   if (ks == kKindAll) return true;
   if (is_net_kind(ks)) return c < kNetClasses;
-  return c == kNetClasses + (ks - kKindRss16);
+  return c == rss_class_of(ks);
 }
 
 // Runs tile `tile_in_class` of class c (only the handlers of kind set KS are
@@ -490,19 +510,24 @@ __device__ __forceinline__ void run_tile(unsigned char* wave_lds, K* keys, Pay<V
       return;
     }
   }
+  if constexpr (KS == kKindAll || KS == kKindRss8) {
+    if (c == kNetClasses)
+      rss_tile<F, K, V, 8>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0],
+                           a.cfg);
+  }
   if constexpr (KS == kKindAll || KS == kKindRss16) {
-    if (c == 15)
-      rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[0],
+    if (c == kNetClasses + 1)
+      rss_tile<F, K, V, 16>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1],
                             a.cfg);
   }
   if constexpr (KS == kKindAll || KS == kKindRss32) {
-    if (c == 16)
-      rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[1],
+    if (c == kNetClasses + 2)
+      rss_tile<F, K, V, 32>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2],
                             a.cfg);
   }
   if constexpr (KS == kKindAll || KS == kKindRss64) {
-    if (c == 17)
-      rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[2],
+    if (c == kNetClasses + 3)
+      rss_tile<F, K, V, 64>(wave_lds, keys, vals, a.offsets, a.ids, list, count, first, rounds, flip, a.k0[3],
                             a.cfg);
   }
 }
@@ -566,14 +591,15 @@ template <class K, int V, int KS> struct PersistWaves {
   static constexpr int kType = (sizeof(K) == 8 ? 2 : 0) + (V ? 1 : 0);  // u32, u32+v, u64, u64+v
   static constexpr int value = KS == kKindAll   ? (kType == 0 ? 5 : (kType == 3 ? 3 : 4))
                                : is_net_kind(KS) ? 1
-                               : kType == 0     ? (KS == kKindRss16 ? 7 : 6)
-                               : (kType == 1 && KS == kKindRss16) ? 5
+                               : kType == 0     ? (KS == kKindRss16 || KS == kKindRss8 ? 7 : 6)
+                               : (kType == 1 && (KS == kKindRss16 || KS == kKindRss8)) ? 5
                                                                   : 4;
 };
 
 template <class K, int V, int KS> struct PersistLds {
   static constexpr size_t kBytes = KS == kKindNet    ? 16
                                    : KS == kKindNetMix ? sizeof(NetLds<K, V>)
+                                   : KS == kKindRss8  ? 8 * sizeof(GroupLds<K, V, 8>)
                                    : KS == kKindRss16 ? 4 * sizeof(GroupLds<K, V, 16>)
                                    : KS == kKindRss32 ? 2 * sizeof(GroupLds<K, V, 32>)
                                    : KS == kKindRss64 ? sizeof(GroupLds<K, V, 64>)
@@ -596,7 +622,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
   const int wi = ((int)blockIdx.x / kTileParts) * kSortWaves + wave;  // wave index within the partition
   uint32_t* counter = &ctrl[kCtrlTile + (KS * kTileParts + part) * 32];
 
-  constexpr bool kSingle = KS >= kKindRss16 && KS <= kKindRss64;
+  constexpr bool kSingle = is_rss_kind(KS);
   if constexpr (kSingle) {
     // One RSS class, in units of one round (one array per lane group).
     // Partition p owns a contiguous range of units; its waves take chunks of
@@ -604,12 +630,12 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
     // wave -- in pieces of a quarter chunk claimed from the partition's
     // counter, so the waves finish within about a quarter chunk of each
     // other.
-    constexpr int kClass = kNetClasses + (KS - kKindRss16);
-    constexpr int G = KS == kKindRss16 ? 16 : (KS == kKindRss32 ? 32 : 64);
+    constexpr int kClass = rss_class_of(KS);
+    constexpr int G = rss_group(kClass);
     constexpr int kGroups = kWave / G;
     const int count = (int)a.ctrl[kCtrlCount + kClass];
     const int list = (int)a.ctrl[kCtrlStart + kClass];
-    const int k0 = a.k0[KS - kKindRss16];
+    const int k0 = a.k0[kClass - kNetClasses];
     auto run_units = [&](int u, int n) __attribute__((always_inline)) {
       rss_tile<F, K, V, G>(lds[wave], keys, vals, a.offsets, a.ids, list, count, u * kGroups, n, flip, k0, a.cfg);
     };
@@ -650,7 +676,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
 #pragma unroll
     for (int o = 0; o < kNetClasses; ++o) {
       net_first[o] = acc;
-      acc += class_tiles<KS>(a.ctrl, class_at(3 + o), a.rounds, waves);
+      acc += class_tiles<KS>(a.ctrl, class_at(kRssClasses + o), a.rounds, waves);
     }
     net_first[kNetClasses] = acc;
   }
@@ -666,7 +692,7 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
 #pragma unroll
       for (int o = 0; o < kNetClasses; ++o) {
         if (t >= net_first[o] && t < net_first[o + 1]) {
-          c = class_at(3 + o);
+          c = class_at(kRssClasses + o);
           idx = t - net_first[o];
         }
       }
@@ -698,9 +724,9 @@ seg_persistent_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs 
 }
 
 // Plain baseline: one launch per class, tile = blockIdx * waves + wave.  The
-// kernel is specialised per handler (KIND 0: networks, 1..3: RSS with 16-,
-// 32-, 64-lane groups), so each launch carries only its own code and
-// registers.
+// kernel is specialised per handler (KIND 0: networks, 1..4: the RSS classes
+// 15..18, with 8-, 16-, 32-, 64-lane groups), so each launch carries only its
+// own code and registers.
 template <int F, class K, int V, int KIND>
 __global__ void __launch_bounds__(kSortThreads)
 seg_class_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, KeyMap<K> flip, int c, int count,
@@ -712,15 +738,10 @@ seg_class_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, Ke
   const int first = tile * class_tile(c, rounds);
   if constexpr (KIND == 0) {
     net_tile_dispatch<F, K, V>(c + 2, keys, vals, a.offsets, a.ids, list, count, first, flip);
-  } else if constexpr (KIND == 1) {
-    rss_tile<F, K, V, 16>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[0], a.cfg);
-  } else if constexpr (KIND == 2) {
-    rss_tile<F, K, V, 32>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[1], a.cfg);
   } else {
-    rss_tile<F, K, V, 64>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
-                          a.k0[2], a.cfg);
+    constexpr int kClass = kNetClasses + KIND - 1;
+    rss_tile<F, K, V, rss_group(kClass)>(lds[wave], keys, vals, a.offsets, a.ids, list, count, first, rounds, flip,
+                                         a.k0[KIND - 1], a.cfg);
   }
 }
 
@@ -742,7 +763,7 @@ seg_large_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, Ke
       if (threadIdx.x == 0) insertion_sort_global<K, V>(keys + lo, V ? vals + lo : nullptr, m, flip);
       continue;
     }
-    large_sort<F, K, V>(large_lds, keys + lo, V ? vals + lo : nullptr, m, flip, a.k0[2], a.cfg);
+    large_sort<F, K, V>(large_lds, keys + lo, V ? vals + lo : nullptr, m, flip, a.k0[3], a.cfg);
   }
 }
 
@@ -769,8 +790,8 @@ __global__ void __launch_bounds__(kSortThreads)
 seg_is_kernel(K* __restrict__ keys, Pay<V>* __restrict__ vals, SortArgs a, uint32_t* ctrl, KeyMap<K> flip) {
   (void)ctrl;
   const int list = (int)a.ctrl[kCtrlStart + kNetClasses];
-  const int count = (int)(a.ctrl[kCtrlCount + kNetClasses] + a.ctrl[kCtrlCount + kNetClasses + 1] +
-                          a.ctrl[kCtrlCount + kNetClasses + 2]);
+  int count = 0;
+  for (int c = kNetClasses; c < kNetClasses + kRssClasses; ++c) count += (int)a.ctrl[kCtrlCount + c];
   for (int j = blockIdx.x * kSortThreads + threadIdx.x; j < count; j += gridDim.x * kSortThreads) {
     const int seg = a.ids[list + j];
     const int lo = a.offsets[seg];
@@ -784,7 +805,7 @@ struct GraphEntry {
   int key = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t nodes[8] = {};  // count, scan, scatter, the persistent kernel(s), the large class
+  hipGraphNode_t nodes[9] = {};  // count, scan, scatter, the persistent kernel(s), the large class
   int nnodes = 0;
   int persist_blocks[kKinds] = {};
 };
@@ -837,11 +858,13 @@ inline SortArgs make_args(const int32_t* offsets, const SegBuffers& s) {
   a.ctrl = s.ctrl;
   a.rounds = t.rss_rounds;
   a.waves = 1;
-  a.k0[0] = t.rss_k[0];
-  a.k0[1] = t.rss_k[1];
-  a.k0[2] = t.rss_k[2];
+  a.k0[0] = 8;  // the 8-lane class: every first level has 8 buckets
+  a.k0[1] = t.rss_k[0];
+  a.k0[2] = t.rss_k[1];
+  a.k0[3] = t.rss_k[2];
   a.interleave = t.interleave;
   a.net_mix = t.net_mix;
+  a.bound_tiny = t.rss_bound_tiny;
   a.bound_small = t.rss_bound_small;
   a.bound_mid = t.rss_bound_mid;
   a.cfg = RssCfg{t.rss_level_cap, t.rss_oversample, t.rss_finish};
@@ -881,11 +904,11 @@ struct SegLaunch {
 
   bool is_rss;  // large_sort: one insertion-sort kernel replaces the RSS kernels (split form only)
 
-  int nnodes() const { return split ? (is_rss ? 6 : 8) : 5; }
+  int nnodes() const { return split ? (is_rss ? 6 : 9) : 5; }
   // kind set of node i >= 3: network classes, then the RSS classes largest first
   int node_kind(int i) const {
     if (!split) return kKindAll;
-    static constexpr int order[4] = {kKindNet, kKindRss64, kKindRss32, kKindRss16};
+    static constexpr int order[5] = {kKindNet, kKindRss64, kKindRss32, kKindRss16, kKindRss8};
     return (i == 3 && mix) ? kKindNetMix : order[i - 3];
   }
 
@@ -904,7 +927,7 @@ struct SegLaunch {
     args = make_args<K>(off, s);
     flip = fl;
     mix = args.net_mix;
-    bins = pack_bins(mix, args.bound_small, args.bound_mid);
+    bins = pack_bins(mix, args.bound_tiny, args.bound_small, args.bound_mid);
     p_count[0] = &offsets; p_count[1] = &nseg; p_count[2] = &blockhist; p_count[3] = &status; p_count[4] = &bins;
     p_scan[0] = &blockhist; p_scan[1] = &nblocks; p_scan[2] = &ctrl;
     p_scatter[0] = &offsets; p_scatter[1] = &nseg; p_scatter[2] = &blockbase; p_scatter[3] = &ctrl_c;
@@ -917,6 +940,7 @@ struct SegLaunch {
     switch (ks) {
       case kKindNet: return (void*)seg_persistent_kernel<F, K, V, kKindNet>;
       case kKindNetMix: return (void*)seg_persistent_kernel<F, K, V, kKindNetMix>;
+      case kKindRss8: return (void*)seg_persistent_kernel<F, K, V, kKindRss8>;
       case kKindRss16: return (void*)seg_persistent_kernel<F, K, V, kKindRss16>;
       case kKindRss32: return (void*)seg_persistent_kernel<F, K, V, kKindRss32>;
       case kKindRss64: return (void*)seg_persistent_kernel<F, K, V, kKindRss64>;
@@ -998,14 +1022,14 @@ template <int F, class K, int V>
 static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>& L, hipStream_t s) {
   // resident waves of one per-class launch (largest RSS class kernel)
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_class_kernel<F, K, V, 3>, kSortThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, seg_class_kernel<F, K, V, kRssClasses>, kSortThreads, 0) !=
           hipSuccess ||
       nb <= 0)
     nb = 2;
   L.args.waves = nb * c->num_cus * kSortWaves;
   L.args.net_mix = 0;  // the baseline launches one kernel per network size
   L.mix = 0;
-  L.bins = pack_bins(0, L.args.bound_small, L.args.bound_mid);
+  L.bins = pack_bins(0, L.args.bound_tiny, L.args.bound_small, L.args.bound_mid);
   hipError_t e = L.launch_binning(s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sc->host_ctrl, sc->ctrl, (kCtrlStart + kClasses) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
@@ -1023,19 +1047,22 @@ static hipError_t run_plain(DeviceCtx* c, SegmentedCache* sc, SegLaunch<F, K, V>
     if (cls < kNetClasses)
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 0>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
-    else if (cls == 15)
+    else if (cls == kNetClasses)
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 1>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
-    else if (cls == 16)
+    else if (cls == kNetClasses + 1)
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 2>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
-    else
+    else if (cls == kNetClasses + 2)
       hipLaunchKernelGGL((seg_class_kernel<F, K, V, 3>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
+                         L.args, L.flip, cls, count, list);
+    else
+      hipLaunchKernelGGL((seg_class_kernel<F, K, V, 4>), dim3(blocks), dim3(kSortThreads), 0, s, L.keys, L.vals,
                          L.args, L.flip, cls, count, list);
   }
   if (L.is_rss) {
-    const int nrss = (int)(sc->host_ctrl[kCtrlCount + 15] + sc->host_ctrl[kCtrlCount + 16] +
-                           sc->host_ctrl[kCtrlCount + 17]);
+    int nrss = 0;
+    for (int c = kNetClasses; c < kNetClasses + kRssClasses; ++c) nrss += (int)sc->host_ctrl[kCtrlCount + c];
     if (nrss > 0)
       hipLaunchKernelGGL((seg_is_kernel<K, V>), dim3((nrss + kSortThreads - 1) / kSortThreads), dim3(kSortThreads), 0,
                          s, L.keys, L.vals, L.args, L.ctrl, L.flip);
@@ -1094,6 +1121,7 @@ static void init_launch(DeviceCtx* c, SegLaunch<F, K, V>& L) {
   if (L.split) {
     L.persist_blocks[kKindNet] = persistent_blocks<F, K, V, kKindNet>(c);
     L.persist_blocks[kKindNetMix] = persistent_blocks<F, K, V, kKindNetMix>(c);
+    L.persist_blocks[kKindRss8] = persistent_blocks<F, K, V, kKindRss8>(c);
     L.persist_blocks[kKindRss16] = persistent_blocks<F, K, V, kKindRss16>(c);
     L.persist_blocks[kKindRss32] = persistent_blocks<F, K, V, kKindRss32>(c);
     L.persist_blocks[kKindRss64] = persistent_blocks<F, K, V, kKindRss64>(c);

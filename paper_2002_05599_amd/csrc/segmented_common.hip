@@ -97,7 +97,7 @@ seg_scatter_kernel(const int32_t* __restrict__ offsets, int32_t nseg, const uint
 //
 // One array per device, held from code-object load until the process ends:
 // the control block, the binning histogram and a segment-id list for up to
-// kNoAllocMaxSeg segments (64 MiB + 80 KiB).  Every no-allocation call on a
+// kNoAllocMaxSeg segments (64 MiB + 88 KiB).  Every no-allocation call on a
 // device uses the same array, so such calls must not overlap on one device.
 // Nothing in it needs clearing between calls: the count kernel writes every
 // histogram entry, the scan kernel writes the class counts and starts and

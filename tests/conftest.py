@@ -9,8 +9,8 @@ if ROOT not in sys.path:
 
 # every tuning knob the library exposes (include/smallsort.h); the per-width
 # ones are snapshot per width
-PER_WIDTH_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "rss_bound_small", "rss_bound_mid",
-                   "rss_oversample", "fixed_apt", "rss_finish")
+PER_WIDTH_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "rss_bound_tiny", "rss_bound_small",
+                   "rss_bound_mid", "rss_oversample", "fixed_apt", "rss_finish")
 GLOBAL_KNOBS = ("persist_occ", "rss_rounds", "interleave", "persist_split", "net_mix", "rss_level_cap",
                 "large_sort")
 TUNING_KNOBS = tuple(f"{w}.{k}" for k in PER_WIDTH_KNOBS for w in ("u32", "u64")) + GLOBAL_KNOBS
@@ -31,14 +31,16 @@ def _restore_tuning():
         return
     before = {k: ss.get_tuning(k) for k in TUNING_KNOBS}
     yield
-    # bounds first lowered then raised in an order that keeps small <= mid valid
-    for k in sorted(before, key=lambda k: (not k.endswith("rss_bound_mid"), k)):
-        v = before[k]
-        if v >= 0 and ss.get_tuning(k) != v:
-            try:
-                ss.set_tuning(k, v)
-            except ss.SmallSortError:
-                pass
+    # the lane-group bounds must stay ordered (tiny <= small <= mid) at every
+    # step: a few lenient passes reach any target order
+    for _ in range(3):
+        for k in sorted(before, key=lambda k: (not k.endswith("rss_bound_mid"), k)):
+            v = before[k]
+            if v >= 0 and ss.get_tuning(k) != v:
+                try:
+                    ss.set_tuning(k, v)
+                except ss.SmallSortError:
+                    pass
     for k, v in before.items():
         if v >= 0 and ss.get_tuning(k) != v:
             ss.set_tuning(k, v)

@@ -56,13 +56,20 @@ class tuned:
         for k in self.knobs:  # per-width knobs are restored per width
             for name in ((f"u32.{k}", f"u64.{k}") if ss.get_tuning(f"u32.{k}") >= 0 else (k,)):
                 self.old[name] = ss.get_tuning(name)
+        # ordered knobs (the lane-group bounds) may need another pass
+        for _ in range(2):
+            for k, v in self.knobs.items():
+                try:
+                    ss.set_tuning(k, v)
+                except ss.SmallSortError:
+                    pass
         for k, v in self.knobs.items():
             ss.set_tuning(k, v)
         return self
 
     def __exit__(self, *exc):
         import paper_2002_05599_amd as ss
-        for _ in range(2):  # twice: a bound may only be valid once the other is back
+        for _ in range(3):  # a bound may only be valid once the others are back
             for k, v in self.old.items():
                 try:
                     ss.set_tuning(k, v)

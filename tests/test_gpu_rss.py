@@ -84,33 +84,36 @@ def test_rss_every_size_u32():
         assert (got == want).all(), f"n={n}: {first_mismatch(got, want, n)}"
 
 
-TUNINGS = [("rss_k_small", 4), ("rss_k_small", 8), ("rss_k_small", 16),
-           ("rss_k_mid", 4), ("rss_k_mid", 8), ("rss_k_mid", 16), ("rss_k_mid", 32),
-           ("rss_k_large", 4), ("rss_k_large", 8), ("rss_k_large", 16), ("rss_k_large", 32),
-           ("rss_k_large", 64), ("family", 0), ("family", 1), ("family", 2), ("large_sort", 1),
-           ("rss_oversample", 1), ("rss_oversample", 2), ("rss_oversample", 4),
-           ("rss_bound_small", 16), ("rss_bound_small", 32), ("rss_bound_small", 48),
-           ("rss_bound_mid", 96), ("rss_bound_mid", 64), ("rss_finish", 1)]
+TUNINGS = [dict(rss_k_small=4), dict(rss_k_small=8), dict(rss_k_small=16),
+           dict(rss_k_mid=4), dict(rss_k_mid=8), dict(rss_k_mid=16), dict(rss_k_mid=32),
+           dict(rss_k_large=4), dict(rss_k_large=8), dict(rss_k_large=16), dict(rss_k_large=32),
+           dict(rss_k_large=64), dict(family=0), dict(family=1), dict(family=2), dict(large_sort=1),
+           dict(rss_oversample=1), dict(rss_oversample=2), dict(rss_oversample=4),
+           dict(rss_bound_tiny=16, rss_bound_small=16), dict(rss_bound_tiny=16, rss_bound_small=32),
+           dict(rss_bound_tiny=16, rss_bound_small=48), dict(rss_bound_mid=96), dict(rss_bound_mid=64),
+           dict(rss_finish=1), dict(rss_bound_tiny=32), dict(rss_bound_tiny=24),
+           dict(rss_bound_tiny=32, family=2), dict(rss_bound_tiny=32, rss_finish=1),
+           dict(rss_bound_tiny=32, rss_oversample=4), dict(rss_bound_tiny=16)]
 
 
-@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: f"{t[0]}={t[1]}")
+@pytest.mark.parametrize("tuning", TUNINGS, ids=lambda t: "-".join(f"{k}={v}" for k, v in t.items()))
 def test_rss_tuning_variants(tuning):
     """Every first-level bucket count and family (2: buckets finished by
     insertion sort), and insertion sort in place of RSS (large_sort=1, the
-    IS+SN hybrid): uniform keys of every class, duplicate-heavy keys
+    IS+SN hybrid), the lane-group mappings (8-lane groups up to 16..32 keys)
+    and bucket finishes: uniform keys of every class, duplicate-heavy keys
     (three-way splits) and 64-bit keys."""
     from helpers import tuned
-    name, value = tuning
-    with tuned(**{name: value}):
-        for n in (20, 33, 48, 64, 65, 100, 128, 129, 200, 256):
+    with tuned(**tuning):
+        for n in (17, 20, 24, 32, 33, 48, 64, 65, 100, 128, 129, 200, 256):
             a = inputs.random_keys(np.int32, n * 50, seed=n)
             got = run_fixed(a, n, 50, n)
-            assert (got == oracle.sort_fixed(a, n, 50, n)).all(), (name, value, n)
+            assert (got == oracle.sort_fixed(a, n, 50, n)).all(), (tuning, n)
             for kind in ("zipf", "two_values", "one_big_dup", "max_heavy"):
                 a = special(np.uint64, n, 21, kind, seed=n + 1)
                 got = run_fixed(a, n, 21, n)
                 want = oracle.sort_fixed(a, n, 21, n)
-                assert (got == want).all(), (name, value, n, kind, first_mismatch(got, want, n))
+                assert (got == want).all(), (tuning, n, kind, first_mismatch(got, want, n))
 
 
 def test_rss_stride_and_repeat():
@@ -121,19 +124,20 @@ def test_rss_stride_and_repeat():
     assert (run_fixed(a, n, count, stride) == got).all()
 
 
+@pytest.mark.parametrize("tiny", [16, 32])
 @pytest.mark.parametrize("finish", [0, 1])
 @pytest.mark.parametrize("cap", [1, 2])
 @pytest.mark.parametrize("kind", ["uniform", "zipf", "two_values", "max_heavy", "one_big_dup"])
-def test_rss_level_cap_fallback_fixed(cap, kind, finish):
+def test_rss_level_cap_fallback_fixed(cap, kind, finish, tiny):
     """Register Sample Sort stopped after `cap` levels: every bucket still above
     16 keys goes through the rank-counting fallback.  With a first level of 4
     buckets, arrays of 65..256 keys always leave such buckets, so the fallback
     runs on every array of those sizes; with both bucket finishes (the
     rank-counting finish must leave the fallback's buckets in place)."""
     from helpers import tuned
-    with tuned(rss_level_cap=cap, rss_k_small=4, rss_k_mid=4, rss_k_large=4, rss_finish=finish):
+    with tuned(rss_level_cap=cap, rss_k_small=4, rss_k_mid=4, rss_k_large=4, rss_finish=finish, rss_bound_tiny=tiny):
         for dtype in (np.uint32, np.int64):
-            for n in (17, 40, 64, 100, 128, 200, 256):
+            for n in (17, 24, 32, 40, 64, 100, 128, 200, 256):
                 count = 37
                 if kind == "uniform":
                     a = inputs.fixed_keys(dtype, n, count, "uniform", seed=3 * n + cap)

@@ -383,10 +383,17 @@ def test_insertion_sort_above_16_segmented(mode):
         assert ss.device_status() == 0
 
 
-MAPPINGS = [dict(rss_bound_small=16, rss_bound_mid=64), dict(rss_bound_small=32, rss_bound_mid=96),
-            dict(rss_bound_small=48, rss_bound_mid=128), dict(rss_bound_small=64, rss_bound_mid=64),
+MAPPINGS = [dict(rss_bound_tiny=16, rss_bound_small=16, rss_bound_mid=64),
+            dict(rss_bound_tiny=16, rss_bound_small=32, rss_bound_mid=96),
+            dict(rss_bound_tiny=16, rss_bound_small=48, rss_bound_mid=128),
+            dict(rss_bound_tiny=16, rss_bound_small=64, rss_bound_mid=64),
+            dict(rss_bound_tiny=32, rss_bound_small=64, rss_bound_mid=128),
+            dict(rss_bound_tiny=24, rss_bound_small=40, rss_bound_mid=128),
+            dict(rss_bound_tiny=32, rss_bound_small=32, rss_bound_mid=32),
             dict(rss_oversample=1), dict(rss_oversample=4), dict(rss_finish=0), dict(rss_finish=1),
-            dict(rss_finish=1, rss_bound_small=16, rss_bound_mid=64)]
+            dict(rss_finish=1, rss_bound_tiny=16, rss_bound_small=16, rss_bound_mid=64),
+            dict(rss_finish=1, rss_bound_tiny=32, rss_bound_small=64, rss_bound_mid=128),
+            dict(rss_finish=0, rss_bound_tiny=32, rss_oversample=4)]
 
 
 @pytest.mark.parametrize("knobs", MAPPINGS, ids=lambda k: "-".join(f"{a}{b}" for a, b in k.items()))
