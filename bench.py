@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extras", action="store_true", help="headline workload only")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--family", type=int, choices=(0, 1), default=None,
+                   help="network family of the fixed-layout workloads (default: the tuned one)")
     p.add_argument("--extras-out", default=os.path.join(ROOT, "gpurun_out", "bench_extras.json"),
                    help="file for the extra workloads' results (also printed one per line)")
     return p.parse_args()
@@ -77,13 +79,14 @@ def kernel_source_hash(kernel_key):
 
 def traffic_for(kernel_key, family):
     """HBM bytes per launch from profiles/traffic.json, if the counters were taken
-    on the same kernel: unchanged sources and the same network family."""
+    on the same kernel: unchanged sources and the same network family (one
+    record per family)."""
     try:
         data = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     except (OSError, ValueError):
         return None
-    ent = data.get(kernel_key)
-    if not ent or ent.get("source_hash") != kernel_source_hash(kernel_key) or ent.get("family") != family:
+    ent = data.get(kernel_key, {}).get(f"family {family}")
+    if not ent or ent.get("source_hash") != kernel_source_hash(kernel_key):
         return None
     return ent.get("bytes_per_launch")
 
@@ -638,6 +641,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.family is not None:
+        import paper_2002_05599_amd as ss
+        ss.set_tuning("family", args.family)
     w = args.workload
     if w in ("all", "fixed16_u32"):
         ceiling = bench_copy_ceiling(args)

@@ -8,11 +8,13 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
   family           network family or insertion sort (fixed arrays of 4..16 keys
                    plus the RSS batches, whose buckets the networks finish)
   fixed_apt        arrays per thread of the fixed-layout kernels (items per
-                   thread; fixed arrays of 2..8 keys)
+                   thread; fixed arrays of 2..16 keys: it applies wherever the
+                   tile of several arrays per thread fits)
   rss_bound_tiny, rss_bound_small, rss_bound_mid
                    the wave-to-segment mapping: which segment sizes get 8, 16,
                    32 or 64 lanes (CSR batches of 17..256, 17..64 and 65..128
-                   keys, and a ragged batch of geometric sizes, mean 24)
+                   keys, and a ragged batch of geometric sizes, mean 24: for
+                   64-bit keys the 10^7-segment batch of the global knobs)
   rss_k_small/mid/large
                    first-level bucket count of each lane-group class (a CSR
                    batch of sizes within the class)
@@ -144,14 +146,23 @@ class Workloads:
         from . import inputs, segmented_sort
         d = 4 if quick else 1
         self.cases = {}
+        # the ragged batch (u64 + payload, 10^7 geometric segments): a workload
+        # of the global knobs and of the 64-bit lane-group mapping
+        k, v, off = inputs.config4(nseg=10_000_000 // d, seed=44)
+        to = torch.from_numpy(off).cuda()
+        ragged = Case("ragged 10^7 u64+payload", lambda b: segmented_sort(b[0], to, b[1]),
+                      [torch.from_numpy(k).cuda(), torch.from_numpy(v).cuda()],
+                      24 * int(off[-1]) + 4 * (off.size - 1))
+        del k, v
         for w in ("u32", "u64"):
             self.cases[(w, "family")] = ([_fixed_case(w, n, (1 << 22) // d, n) for n in (4, 8, 12, 16)]
                                          + [_csr_case(w, (1 << 18) // d, 17, 256, 5)])
-            self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8)]
+            self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8, 12, 16)]
             # the mapping is tuned on the whole RSS range and on each group size's own range
             nr = (1 << 21) // d
             bounds = [_csr_case(w, (1 << 19) // d, 17, 256, 7), _csr_case(w, (1 << 18) // d, 17, 64, 8),
                       _csr_case(w, (1 << 18) // d, 65, 128, 10),
+                      ragged if w == "u64" else
                       _csr_case(w, nr, 1, 256, 11, sizes=inputs.geometric_sizes(nr, 11), what="ragged, mean 24")]
             self.cases[(w, "rss_bound_tiny")] = bounds
             self.cases[(w, "rss_bound_small")] = bounds
@@ -162,11 +173,6 @@ class Workloads:
             self.cases[(w, "rss_oversample")] = [_csr_case(w, (1 << 19) // d, 17, 256, 9)]
             self.cases[(w, "rss_finish")] = self.cases[(w, "rss_oversample")]
         # global knobs: the ragged batch (u64 + payload) and the RSS-only batch (int32)
-        k, v, off = inputs.config4(nseg=10_000_000 // d, seed=44)
-        to = torch.from_numpy(off).cuda()
-        ragged = Case("ragged 10^7 u64+payload", lambda b: segmented_sort(b[0], to, b[1]),
-                      [torch.from_numpy(k).cuda(), torch.from_numpy(v).cuda()],
-                      24 * int(off[-1]) + 4 * (off.size - 1))
         k3, off3 = inputs.config3(nseg=(1 << 20) // d, dist="uniform", seed=7)
         to3 = torch.from_numpy(off3).cuda()
         rss = Case("RSS 2^20 int32", lambda b: segmented_sort(b[0], to3), [torch.from_numpy(k3).cuda()],
