@@ -292,8 +292,12 @@ class tuned:
                     set_tuning(k, v)
                 except SmallSortError:
                     pass
-        for k, v in self.knobs.items():
-            set_tuning(k, v)
+        try:
+            for k, v in self.knobs.items():
+                set_tuning(k, v)
+        except SmallSortError:
+            self.__exit__(None, None, None)  # leave no knob half-set
+            raise
         return self
 
     def __exit__(self, *exc):

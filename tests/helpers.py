@@ -63,8 +63,12 @@ class tuned:
                     ss.set_tuning(k, v)
                 except ss.SmallSortError:
                     pass
-        for k, v in self.knobs.items():
-            ss.set_tuning(k, v)
+        try:
+            for k, v in self.knobs.items():
+                ss.set_tuning(k, v)
+        except ss.SmallSortError:
+            self.__exit__(None, None, None)  # leave no knob half-set
+            raise
         return self
 
     def __exit__(self, *exc):
