@@ -2,13 +2,18 @@
 //
 // Section 5 names merge sort with merging networks as the way to build on the
 // small sorters for larger inputs.  Here the array is cut into runs of 256
-// keys; each wave sorts its runs with Register Sample Sort (the same G = 64
+// keys (128 for arrays of at most 512 keys, so that all four waves have a
+// run); each wave sorts its runs with Register Sample Sort (the same G = 64
 // group sort as the 129..256-key class), and the sorted runs are then merged
 // pairwise in LDS, doubling the run length each round (at most four rounds
-// for 4096 keys).  In a merge round every thread produces 16 consecutive
-// outputs: it finds where its first output's diagonal crosses the two runs by
-// a binary search (merge path; ties are taken from the left run first) and
-// then merges 16 items sequentially.
+// for 4096 keys).  In a merge round every thread produces the same number P
+// of consecutive outputs, the smallest power of two that lets the 256 threads
+// cover the array (2 for up to 512 keys, 16 for 4096).  It finds where its
+// first output's diagonal crosses the two runs by a binary search (merge
+// path; ties are taken from the left run first) and then merges its items
+// sequentially, holding the next key of each run in registers so that a step
+// reads one key from LDS.  (Reading both runs' next P keys at once and
+// ordering them with a bitonic merge in registers was measured no faster.)
 //
 // LDS holds two buffers of kMaxLargeN items (keys as order-preserving words,
 // then payloads).  The second buffer also holds the waves' Register Sample
@@ -22,7 +27,8 @@ namespace ss {
 constexpr int kLargeThreads = 256;
 constexpr int kMaxLargeN = 4096;
 constexpr int kRunN = 256;                               // keys per run (one G = 64 group)
-constexpr int kMergePer = kMaxLargeN / kLargeThreads;    // merge outputs per thread
+constexpr int kShortRunN = kRunN / 2;                    // keys per run for arrays of at most 2 kRunN
+constexpr int kMergePerMax = kMaxLargeN / kLargeThreads;  // merge outputs per thread at 4096 keys
 
 template <class K, int V> struct LargeLds {
   static constexpr size_t kKeyBytes = (size_t)kMaxLargeN * sizeof(K);
@@ -32,6 +38,46 @@ template <class K, int V> struct LargeLds {
   // the second buffer also holds the run sorts' state
   static constexpr size_t kBytes = kBufBytes + (kGroupBytes > kBufBytes ? kGroupBytes : kBufBytes);
 };
+
+// One thread's share of a merge round: outputs out0 .. out0 + P - 1 of the
+// merge of the run pair that holds them (P divides 2L, so a share never spans
+// two pairs).  sk/sv hold runs of L sorted words, dk/dv receive runs of 2L.
+template <int P, class K, int V>
+__device__ __forceinline__ void merge_block(const K* sk, const Pay<V>* sv, K* dk, Pay<V>* dv, int m, int L) {
+  const int out0 = (int)threadIdx.x * P;
+  if (out0 >= m) return;
+  const int a0 = (out0 / (2 * L)) * (2 * L);
+  const int la = min(L, m - a0);  // >= 1
+  const int b0 = a0 + la;
+  const int lb = min(L, m - b0);  // 0 for a last run without partner
+  const int d = out0 - a0;
+  // merge path: i keys of the left run among the first d outputs
+  int lo = max(0, d - lb), hi = min(d, la);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sk[a0 + mid] <= sk[b0 + d - 1 - mid])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int i = lo, j = d - lo;
+  const int n_out = min(P, la + lb - d);
+  // the next key of each run (la >= 1; a key read past a run's end is never used)
+  K ka = sk[a0 + min(i, la - 1)];
+  K kb = lb > 0 ? sk[b0 + min(j, lb - 1)] : K(0);
+  for (int e = 0; e < n_out; ++e) {
+    const bool take_a = i < la && (j >= lb || ka <= kb);
+    const int src = take_a ? a0 + i : b0 + j;
+    dk[out0 + e] = take_a ? ka : kb;
+    if constexpr (V) dv[out0 + e] = sv[src];
+    i += take_a ? 1 : 0;
+    j += take_a ? 0 : 1;
+    // refill from the run that gave its key
+    const K kn = sk[take_a ? a0 + min(i, la - 1) : b0 + min(j, max(lb - 1, 0))];
+    ka = take_a ? kn : ka;
+    kb = take_a ? kb : kn;
+  }
+}
 
 // Sorts the m (<= kMaxLargeN) keys at gk (and payloads at gv) with the whole
 // work-group; every thread of the work-group must call this.
@@ -47,11 +93,13 @@ __device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv
   const int lane = lane_id();
   auto* group = reinterpret_cast<GroupLds<K, V, 64>*>(lds + LL::kBufBytes) + wave;
 
-  // runs of 256 keys, run r by wave r mod 4
-  const int nruns = (m + kRunN - 1) / kRunN;
+  // runs of 256 keys (128 for up to 512 keys, so that every wave has a run),
+  // run r by wave r mod 4
+  const int run = m <= 2 * kRunN ? kShortRunN : kRunN;
+  const int nruns = (m + run - 1) / run;
   for (int r = wave; r < nruns; r += kLargeThreads / kWave) {
-    const int lo = r * kRunN;
-    const int len = min(kRunN, m - lo);
+    const int lo = r * run;
+    const int len = min(run, m - lo);
     rss_group_load(*group, gk + lo, V ? gv + lo : nullptr, len, flip);
     wave_lds_sync();
     rss_group_sort_lds<F>(*group, len, k0, cfg);
@@ -63,40 +111,21 @@ __device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv
   }
   __syncthreads();
 
-  // merge rounds: runs of length L in buffer `cur` -> runs of 2L in the other
+  // merge rounds: runs of length L in buffer `cur` -> runs of 2L in the other;
+  // P outputs per thread, a power of two that divides 2L (P = 2 while
+  // runs of 128 keys are merged, at most 16 once L >= 256)
+  const int per = m <= 512 ? 2 : (m <= 1024 ? 4 : (m <= 2048 ? 8 : kMergePerMax));
   int cur = 0;
-  for (int L = kRunN; L < m; L *= 2) {
+  for (int L = run; L < m; L *= 2) {
     const K* sk = key_buf[cur];
     const VT* sv = val_buf[cur];
     K* dk = key_buf[cur ^ 1];
     VT* dv = val_buf[cur ^ 1];
-    const int out0 = (int)threadIdx.x * kMergePer;
-    if (out0 < m) {
-      // the pair of runs holding this thread's outputs (2L is a multiple of kMergePer)
-      const int a0 = (out0 / (2 * L)) * (2 * L);
-      const int la = min(L, m - a0);
-      const int b0 = a0 + la;
-      const int lb = min(L, m - b0);
-      const int d = out0 - a0;
-      // merge path: i keys of the left run among the first d outputs
-      int lo = max(0, d - lb), hi = min(d, la);
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (sk[a0 + mid] <= sk[b0 + d - 1 - mid])
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      int i = lo, j = d - lo;
-      const int n_out = min(kMergePer, la + lb - d);
-      for (int e = 0; e < n_out; ++e) {
-        const bool take_a = i < la && (j >= lb || sk[a0 + i] <= sk[b0 + j]);
-        const int src = take_a ? a0 + i : b0 + j;
-        dk[out0 + e] = sk[src];
-        if constexpr (V) dv[out0 + e] = sv[src];
-        i += take_a ? 1 : 0;
-        j += take_a ? 0 : 1;
-      }
+    switch (per) {
+      case 2: merge_block<2, K, V>(sk, sv, dk, dv, m, L); break;
+      case 4: merge_block<4, K, V>(sk, sv, dk, dv, m, L); break;
+      case 8: merge_block<8, K, V>(sk, sv, dk, dv, m, L); break;
+      default: merge_block<kMergePerMax, K, V>(sk, sv, dk, dv, m, L); break;
     }
     __syncthreads();
     cur ^= 1;

@@ -89,6 +89,30 @@ def test_large_segments_mixed_batch(mode, family):
     assert ss.device_status() == 0
 
 
+@pytest.mark.parametrize("dtype", [np.uint32, np.int32, np.uint64, np.int64], ids=lambda d: np.dtype(d).name)
+def test_large_segments_largest_key_ties(dtype):
+    """Merge shares at the end of a run pair hold slots past both runs; with many
+    keys equal to the type's largest value (one segment made only of them),
+    such a slot never takes the place of a real key or its payload."""
+    rng = np.random.default_rng(14)
+    sizes = np.array([257, 300, 513, 777, 1025, 1500, 2049, 3001, 4095, 4096, 259, 20, 0, 600])
+    off = inputs.offsets_from_sizes(sizes)
+    total = int(off[-1])
+    top = np.iinfo(dtype).max
+    keys = inputs.random_keys(dtype, total, seed=15)
+    keys[rng.random(total) < 0.3] = top
+    keys[off[5]:off[6]] = top
+    v32 = inputs.segment_index_payload(off)
+    payloads = [v32] + ([inputs.splitmix64(16, total)] if keys.itemsize == 8 else [])
+    want, _ = oracle.sort_segments(keys, off, v32)
+    for mode in MODES:
+        for vals in payloads:
+            gk, gv = run_seg(keys, off, vals, mode=mode)
+            assert (gk == want).all(), (mode, first_mismatch(gk, want))
+            assert pairs_multiset_equal(gk, gv, keys, vals, off) is None, mode
+    assert ss.device_status() == 0
+
+
 def test_large_segments_other_knobs():
     """Insertion sort in place of RSS (IS+SN), insertion-sort run finishing, a
     level cap of 1 and a first level of 4 buckets, on large segments."""
