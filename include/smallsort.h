@@ -211,7 +211,7 @@ const char *ss_strerror(ss_status status);
 
 /*
  * Tuning parameters (variant choices found by the autotuner).  The first
- * ten are kept per key width: "<name>" sets both widths, "u32.<name>" or
+ * eleven are kept per key width: "<name>" sets both widths, "u32.<name>" or
  * "u64.<name>" one of them (32-bit keys: uint32, int32, float; 64-bit keys:
  * uint64, int64, double); getting "<name>" returns -2 when the widths differ.
  *   "family"       n <= 16: 0 = fewest-comparator networks, 1 = Bose-Nelson
@@ -230,6 +230,10 @@ const char *ss_strerror(ss_status status);
  *                  with 4 buckets (1..4, default 3: the paper's "332")
  *   "fixed_apt"    arrays per thread of the fixed-layout network kernels (1, 2
  *                  or 4; reduced where the tile would not fit 32 KiB of LDS)
+ *   "fixed_half"   bit mask over n = 2..16 (bit n, 0..0x1FFFC, default 0):
+ *                  where one array per thread is used, arrays of n keys are
+ *                  staged by 128-thread work-groups (half the LDS tile of the
+ *                  256-thread form)
  *   "rss_finish"   how Register Sample Sort finishes its buckets of 2..16
  *                  keys: 0 = one network per bucket (Section 3, default),
  *                  1 = rank counting (each key counts the smaller keys of its

@@ -10,6 +10,9 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
   fixed_apt        arrays per thread of the fixed-layout kernels (items per
                    thread; fixed arrays of 2..16 keys: it applies wherever the
                    tile of several arrays per thread fits)
+  fixed_half       per n = 2..16, whether the one-array-per-thread tile of
+                   arrays of n keys is staged by 128 or by 256 threads (each
+                   bit tuned on its own fixed batch of that n)
   rss_bound_tiny, rss_bound_small, rss_bound_mid
                    the wave-to-segment mapping: which segment sizes get 8, 16,
                    32 or 64 lanes (CSR batches of 17..256, 17..64 and 65..128
@@ -50,7 +53,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
-PER_WIDTH = ("family", "fixed_apt", "rss_bound_tiny", "rss_bound_small", "rss_bound_mid", "rss_k_small", "rss_k_mid",
+PER_WIDTH = ("family", "fixed_apt", "fixed_half", "rss_bound_tiny", "rss_bound_small", "rss_bound_mid", "rss_k_small", "rss_k_mid",
              "rss_k_large", "rss_oversample", "rss_finish")
 GLOBAL = ("rss_rounds", "persist_split", "net_mix", "interleave", "persist_occ")
 NOISE = 0.01
@@ -158,6 +161,7 @@ class Workloads:
             self.cases[(w, "family")] = ([_fixed_case(w, n, (1 << 22) // d, n) for n in (4, 8, 12, 16)]
                                          + [_csr_case(w, (1 << 18) // d, 17, 256, 5)])
             self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8, 12, 16)]
+            self.cases[(w, "fixed_half")] = None  # built one n at a time (fixed_half_case)
             # the mapping is tuned on the whole RSS range and on each group size's own range
             nr = (1 << 21) // d
             bounds = [_csr_case(w, (1 << 19) // d, 17, 256, 7), _csr_case(w, (1 << 18) // d, 17, 64, 8),
@@ -184,7 +188,7 @@ class Workloads:
     def all_cases(self):
         seen = {}
         for cs in self.cases.values():
-            for c in cs:
+            for c in cs or ():
                 seen[id(c)] = c
         return list(seen.values())
 
@@ -198,6 +202,44 @@ def candidates(name):
             "persist_split": [0, 1], "net_mix": [0, 1], "interleave": [0, 1], "persist_occ": [0, 1, 2, 3]}[name]
 
 
+def _tune_half(name, width, quick, reps, log):
+    """The bit mask of n whose one-array-per-thread tile uses 128 threads: each
+    bit is timed on a fixed batch of 2^23 (2^21 quick) arrays of that n, with
+    the other bits as chosen so far, and its output checked against the
+    library's default."""
+    import torch
+    from . import get_tuning, set_tuning
+    d = 4 if quick else 1
+    mask = get_tuning(name)
+    results, rejected = {}, []
+    for n in range(2, 17):
+        case = _fixed_case(width, n, (1 << 23) // d, n)
+        set_tuning(name, mask & ~(1 << n))
+        case.record_reference()
+        times = {}
+        for bit in (0, 1):
+            set_tuning(name, (mask & ~(1 << n)) | (bit << n))
+            ms = case.time(reps)
+            if not case.output_matches():
+                rejected.append(f"n={n} bit={bit}")
+                log(f"  {name} n={n} bit={bit}: output differs from the reference -- rejected")
+                continue
+            times[bit] = ms
+            log(f"  {name} n={n} threads={128 if bit else 256}: {ms:.4f} ms  "
+                f"{case.nbytes / (ms * 1e-3) / 1e9:.1f} GB/s")
+        cur = (mask >> n) & 1
+        pick = min(times, key=times.get) if times else cur
+        if cur in times and times[pick] > (1.0 - NOISE) * times[cur]:
+            pick = cur
+        mask = (mask & ~(1 << n)) | (pick << n)
+        results[f"n={n}"] = {"ms_256": times.get(0), "ms_128": times.get(1), "threads": 128 if pick else 256}
+        del case
+        torch.cuda.empty_cache()
+    set_tuning(name, mask)
+    log(f"{name} -> {mask:#x}")
+    return mask, {"workloads": [f"{width} fixed n=2..16"], "results": results, "rejected": rejected, "best": mask}
+
+
 def tune(quick=False, reps=5, log=print):
     from . import SmallSortError, get_tuning, set_tuning
     w = Workloads(quick=quick)
@@ -208,6 +250,9 @@ def tune(quick=False, reps=5, log=print):
     order = [(wd, k) for wd in ("u32", "u64") for k in PER_WIDTH] + [("all", k) for k in GLOBAL]
     for width, knob in order:
         name = knob if width == "all" else f"{width}.{knob}"
+        if knob == "fixed_half":
+            best[name], report[name] = _tune_half(name, width, quick, reps, log)
+            continue
         current = get_tuning(name)
         cases = w.cases[(width, knob)]
         results, rejected = {}, []

@@ -34,9 +34,9 @@ constexpr int kTileThreads = 256;
 // non-temporal builtins).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Tile of TA = A * 256 arrays (A arrays per thread).
-template <int N, class K, int A = 1> struct TileLayout {
-  static constexpr int TA = A * kTileThreads;
+// Tile of TA = A * TT arrays (A arrays per thread, TT threads).
+template <int N, class K, int A = 1, int TT = kTileThreads> struct TileLayout {
+  static constexpr int TA = A * TT;
   static constexpr int E = (int)sizeof(K);
   static constexpr bool kVec = (N * E) % 16 == 0;
   static constexpr int C = kVec ? N * E / 16 : 1;   // 16-byte chunks per array
@@ -82,15 +82,16 @@ template <class K> __device__ __forceinline__ void lds_st(unsigned char* p, K v)
   *reinterpret_cast<K*>(p) = v;
 }
 
-template <int F, int N, class K, int A>
-__global__ void __launch_bounds__(kTileThreads)
-fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
-  using L = TileLayout<N, K, A>;
+// One tile of TT threads (256, or 128 for a one-array-per-thread tile of half
+// the LDS).
+template <int F, int N, class K, int A, int TT>
+__device__ __forceinline__ void tile_sort(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
+  using L = TileLayout<N, K, A, TT>;
   constexpr int TA = L::TA;
   __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
   constexpr int kChunks = TA * N * L::E / 16;  // 16-byte chunks in a full tile
-  constexpr int kIters = (kChunks + kTileThreads - 1) / kTileThreads;
-  constexpr bool kExact = (kChunks % kTileThreads) == 0;
+  constexpr int kIters = (kChunks + TT - 1) / TT;
+  constexpr bool kExact = (kChunks % TT) == 0;
 
   const int t = threadIdx.x;
   const int64_t first = (int64_t)blockIdx.x * TA;
@@ -104,12 +105,12 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
     u32x4 buf[kIters];
 #pragma unroll
     for (int i = 0; i < kIters; ++i) {
-      int g = t + i * kTileThreads;
+      int g = t + i * TT;
       if (kExact || g < kChunks) buf[i] = __builtin_nontemporal_load(g4 + g);
     }
 #pragma unroll
     for (int i = 0; i < kIters; ++i) {
-      int g = t + i * kTileThreads;
+      int g = t + i * TT;
       if (kExact || g < kChunks) {
         if constexpr (L::kVec) {
           int a = g / L::C, k = g - (g / L::C) * L::C;
@@ -130,7 +131,7 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
     }
   } else {
     const int nelem = valid * N;
-    for (int e = t; e < nelem; e += kTileThreads) {
+    for (int e = t; e < nelem; e += TT) {
       int a = e / N, j = e - (e / N) * N;
       lds_st<K>(lds + L::elem_offset(a, j), gk[e]);
     }
@@ -139,7 +140,7 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
 
 #pragma unroll
   for (int q = 0; q < A; ++q) {
-    const int a = t + q * kTileThreads;  // this thread's q-th array of the tile
+    const int a = t + q * TT;  // this thread's q-th array of the tile
     if (a < valid) {
       K r[N];
       if constexpr (L::kVec) {
@@ -174,7 +175,7 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
     u32x4* g4 = reinterpret_cast<u32x4*>(gk);
 #pragma unroll
     for (int i = 0; i < kIters; ++i) {
-      int g = t + i * kTileThreads;
+      int g = t + i * TT;
       if (kExact || g < kChunks) {
         u32x4 v;
         if constexpr (L::kVec) {
@@ -197,11 +198,30 @@ fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
     }
   } else {
     const int nelem = valid * N;
-    for (int e = t; e < nelem; e += kTileThreads) {
+    for (int e = t; e < nelem; e += TT) {
       int a = e / N, j = e - (e / N) * N;
       gk[e] = lds_ld<K>(lds + L::elem_offset(a, j));
     }
   }
+}
+
+template <int F, int N, class K, int A>
+__global__ void __launch_bounds__(kTileThreads)
+fixed_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
+  tile_sort<F, N, K, A, kTileThreads>(keys, count, flip);
+}
+
+// The one-array-per-thread tile with 128 threads.  A network tile asks for at
+// least kTileMinWaves waves per SIMD, so that the compiler does not trade
+// occupancy for registers (it would hoist every chunk load of a tile of 64-bit
+// keys into registers otherwise); insertion sort keeps the default bound,
+// which avoids spills.
+constexpr int kHalfTileThreads = 128;
+constexpr int kTileMinWaves = 4;
+template <int F, int N, class K>
+__global__ void __launch_bounds__(kHalfTileThreads, F != kFamilyInsertion ? kTileMinWaves : 1)
+fixed_half_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
+  tile_sort<F, N, K, 1, kHalfTileThreads>(keys, count, flip);
 }
 
 // Arrays of 8 bytes (uint32 n = 2): a 16-byte chunk holds two whole arrays,
@@ -262,18 +282,23 @@ fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, KeyMap<
   for (int j = 0; j < N; ++j) p[j] = flip.dec(r[j]);
 }
 
-template <int F, int N, class K, int A>
+template <int F, int N, class K, int A, int TT = kTileThreads>
 static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_t s) {
-  constexpr int64_t TA = (int64_t)A * kTileThreads;
+  constexpr int64_t TA = (int64_t)A * TT;
   const int64_t blocks = (count + TA - 1) / TA;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fixed_tile_kernel<F, N, K, A>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s, keys, count,
-                     flip);
+  if constexpr (TT == kHalfTileThreads) {
+    static_assert(A == 1, "the 128-thread tile holds one array per thread");
+    hipLaunchKernelGGL((fixed_half_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
+  } else {
+    hipLaunchKernelGGL((fixed_tile_kernel<F, N, K, A>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
+  }
   return hipGetLastError();
 }
 
 template <int F, int N, class K>
-static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, int apt, hipStream_t s) {
+static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, int apt, bool half,
+                                 hipStream_t s) {
   const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
@@ -301,6 +326,7 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<
     if constexpr (tile_fits<N, K, 2>()) {
       if (apt >= 2) return launch_tile<F, N, K, 2>(keys, count, flip, s);
     }
+    if (half) return launch_tile<F, N, K, 1, kHalfTileThreads>(keys, count, flip, s);
     return launch_tile<F, N, K, 1>(keys, count, flip, s);
   } else {
     hipLaunchKernelGGL((fixed_direct_kernel<F, N, K>), dim3((unsigned)blocks), dim3(kTileThreads), 0, s,
@@ -311,23 +337,25 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<
 
 template <int F, class K>
 static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, KeyMap<K> flip, hipStream_t s) {
-  const int apt = tuning(sizeof(K)).fixed_apt;
+  const Tuning t = tuning(sizeof(K));
+  const int apt = t.fixed_apt;
+  const bool half = ((t.fixed_half >> n) & 1) != 0;
   switch (n) {
-    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, s);
-    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, s);
-    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, s);
-    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, s);
-    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, s);
-    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, s);
-    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, s);
-    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, s);
-    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, s);
-    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, s);
-    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, s);
-    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, s);
-    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, s);
-    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, s);
-    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, s);
+    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, half, s);
+    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, half, s);
+    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, half, s);
+    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, half, s);
+    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, half, s);
+    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, half, s);
+    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, half, s);
+    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, half, s);
+    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, half, s);
+    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, half, s);
+    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, half, s);
+    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, half, s);
+    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, half, s);
+    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, half, s);
+    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, half, s);
     default: return hipErrorInvalidValue;
   }
 }
