@@ -6,13 +6,15 @@ they are measured on the GPU at hand, separately for 32-bit and 64-bit keys.
 
 Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
   family           network family or insertion sort (fixed arrays of 4..16 keys
-                   plus the RSS batches, whose buckets the networks finish)
+                   plus the RSS batches, whose buckets the networks finish;
+                   for 64-bit keys also the ragged batch)
   fixed_apt        arrays per thread of the fixed-layout kernels (items per
                    thread; fixed arrays of 2..16 keys: it applies wherever the
                    tile of several arrays per thread fits)
   fixed_half       per n = 2..16, whether the one-array-per-thread tile of
                    arrays of n keys is staged by 128 or by 256 threads (each
-                   bit tuned on its own fixed batch of that n)
+                   bit tuned on its own fixed batch of that n, back-to-back
+                   calls, the two forms alternating)
   rss_bound_tiny, rss_bound_small, rss_bound_mid
                    the wave-to-segment mapping: which segment sizes get 8, 16,
                    32 or 64 lanes (CSR batches of 17..256, 17..64 and 65..128
@@ -158,8 +160,10 @@ class Workloads:
                       24 * int(off[-1]) + 4 * (off.size - 1))
         del k, v
         for w in ("u32", "u64"):
+            # (64-bit keys: the ragged batch too, whose RSS kernels finish with the family's networks)
             self.cases[(w, "family")] = ([_fixed_case(w, n, (1 << 22) // d, n) for n in (4, 8, 12, 16)]
-                                         + [_csr_case(w, (1 << 18) // d, 17, 256, 5)])
+                                         + [_csr_case(w, (1 << 18) // d, 17, 256, 5)]
+                                         + ([ragged] if w == "u64" else []))
             self.cases[(w, "fixed_apt")] = [_fixed_case(w, n, (1 << 23) // d, n) for n in (2, 3, 4, 6, 8, 12, 16)]
             self.cases[(w, "fixed_half")] = None  # built one n at a time (fixed_half_case)
             # the mapping is tuned on the whole RSS range and on each group size's own range
@@ -203,36 +207,63 @@ def candidates(name):
 
 
 def _tune_half(name, width, quick, reps, log):
-    """The bit mask of n whose one-array-per-thread tile uses 128 threads: each
-    bit is timed on a fixed batch of 2^23 (2^21 quick) arrays of that n, with
-    the other bits as chosen so far, and its output checked against the
-    library's default."""
+    """The bit mask of n whose one-array-per-thread tile uses 128 threads.  For
+    each n the two forms are compared on one fixed batch of that n (2^24
+    arrays and at least 512 MB, so that the Infinity Cache cannot hold it; a
+    quarter in quick mode) with the other bits as chosen so far: the networks
+    are data-oblivious, so each sample times 8 back-to-back in-place calls,
+    and `reps` samples of the two forms alternate so that drift affects both
+    alike.  Each form's output is checked against the library's default."""
     import torch
     from . import get_tuning, set_tuning
     d = 4 if quick else 1
+    kb = 4 if width == "u32" else 8
     mask = get_tuning(name)
     results, rejected = {}, []
+    stream = torch.cuda.current_stream()
+
+    def sample(case):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(8):
+            case.call(case.bufs)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 8
+
     for n in range(2, 17):
-        case = _fixed_case(width, n, (1 << 23) // d, n)
-        set_tuning(name, mask & ~(1 << n))
+        count = max(1 << 24, (1 << 29) // (n * kb)) // d
+        case = _fixed_case(width, n, count, n)
+        forms = {bit: (mask & ~(1 << n)) | (bit << n) for bit in (0, 1)}
+        set_tuning(name, forms[0])
         case.record_reference()
-        times = {}
+        valid = []
         for bit in (0, 1):
-            set_tuning(name, (mask & ~(1 << n)) | (bit << n))
-            ms = case.time(reps)
-            if not case.output_matches():
+            set_tuning(name, forms[bit])
+            case.restore()
+            case.call(case.bufs)
+            if case.output_matches():
+                valid.append(bit)
+            else:
                 rejected.append(f"n={n} bit={bit}")
                 log(f"  {name} n={n} bit={bit}: output differs from the reference -- rejected")
-                continue
-            times[bit] = ms
+        samples = {bit: [] for bit in valid}
+        for _ in range(reps):
+            for bit in valid:
+                set_tuning(name, forms[bit])
+                samples[bit].append(sample(case))
+        times = {bit: float(np.median(v)) for bit, v in samples.items()}
+        for bit, ms in times.items():
             log(f"  {name} n={n} threads={128 if bit else 256}: {ms:.4f} ms  "
                 f"{case.nbytes / (ms * 1e-3) / 1e9:.1f} GB/s")
         cur = (mask >> n) & 1
         pick = min(times, key=times.get) if times else cur
         if cur in times and times[pick] > (1.0 - NOISE) * times[cur]:
             pick = cur
-        mask = (mask & ~(1 << n)) | (pick << n)
-        results[f"n={n}"] = {"ms_256": times.get(0), "ms_128": times.get(1), "threads": 128 if pick else 256}
+        mask = forms[pick]
+        results[f"n={n}"] = {"arrays": count, "ms_256": times.get(0), "ms_128": times.get(1),
+                             "threads": 128 if pick else 256}
         del case
         torch.cuda.empty_cache()
     set_tuning(name, mask)
