@@ -16,12 +16,22 @@
 //   count     one atomic counter per bucket; an exclusive scan gives the
 //             bucket offsets;
 //   scatter   every key (and payload) to its bucket in the temporary buffer.
+// A level of more than kDsTwoPassBlocks blocks of splitters (about two million
+// keys and up) moves the keys in two passes instead, without one global
+// atomic per key: the first search step alone (the block h of 256 splitters
+// a key falls in, an LDS search) orders the keys by block -- per work-group
+// histograms in LDS, one atomic per block and work-group to reserve its
+// ranges, the keys scattered to the temporary buffer -- and then one
+// work-group per block stages the block's splitters in LDS, counts and
+// scatters its keys to their buckets in the caller's buffer and writes the
+// block's bucket offsets.
 // The buckets are then the segments of one segmented sort (networks, Register
 // Sample Sort, the work-group sort up to 4096 keys), k is chosen so that a
 // bucket holds about 1024 keys.  A range bucket that still holds more than
-// 4096 keys is sorted by the same algorithm, recursively, with the caller's
-// now free buffer as its temporary; equality buckets are left as they are.
-// Finally the temporary buffer is copied back.
+// 4096 keys is sorted by the same algorithm, recursively, with the other
+// buffer as its temporary; equality buckets are left as they are.  Finally
+// the buckets are copied back where the single-pass partition left them in
+// the temporary buffer.
 //
 // The host reads two numbers per level (the count of oversized buckets and
 // their bounds), so the call synchronises its stream; it allocates nothing
@@ -79,12 +89,19 @@ __device__ __forceinline__ int ds_load_top(K* top, const K* __restrict__ spl, in
 // largest power of two <= x (x >= 1)
 __device__ __forceinline__ int ds_pow2_floor(int x) { return 1 << (31 - __builtin_clz((unsigned)x)); }
 
+// blocks whose last splitter is below word e (all their splitters are): 0..nt
+template <class K>
+__device__ __forceinline__ int ds_top(K e, const K* top, int nt) {
+  int tb = 0;
+  for (int step = ds_pow2_floor(nt); step >= 1; step >>= 1)
+    if (tb + step <= nt && top[tb + step - 1] < e) tb += step;
+  return tb;
+}
+
 // bucket of word e: 2j or 2j + 1 with j = #{splitters < e} (see above)
 template <class K>
 __device__ __forceinline__ int ds_bucket(K e, const K* top, int nt, const K* __restrict__ spl, int nspl) {
-  int tb = 0;  // blocks whose last splitter is below e: all their splitters are
-  for (int step = ds_pow2_floor(nt); step >= 1; step >>= 1)
-    if (tb + step <= nt && top[tb + step - 1] < e) tb += step;
+  const int tb = ds_top(e, top, nt);
   int j = min(tb * kDsBlock, nspl);  // every splitter is below e when tb == nt
   if (tb < nt) {
     const int len = min(kDsBlock, nspl - j);
@@ -152,6 +169,228 @@ ds_scatter_kernel(const K* __restrict__ keys, const Pay<V>* __restrict__ vals, i
   }
 }
 
+// --- the two-pass partition ---------------------------------------------------
+//
+// Keys are first ordered by their splitter block h = ds_top (0..nt; h = nt
+// holds the keys above every splitter), then within each block by bucket.
+// Block h < nt covers buckets 2 h 256 .. 2 (h 256 + len) - 1 (len = its
+// splitters); block nt covers the last range bucket 2 nspl alone.  A key of
+// block h < nt is not above the block's last splitter, so its search inside
+// the block ends on a splitter of the block.
+constexpr int kDsTwoPassBlocks = 8;
+
+// Keys per work-group of the first pass (a contiguous chunk each).
+__device__ __forceinline__ void ds_chunk(int64_t n, int64_t& i0, int64_t& i1) {
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  i0 = (int64_t)blockIdx.x * chunk;
+  i1 = min(n, i0 + chunk);
+}
+
+// Calls f(i, key, block) for the keys i0 <= i < i1, kDsUnroll per thread at
+// a time: their searches are independent chains of LDS reads that overlap.
+constexpr int kDsUnroll = 8;
+template <class K, class F>
+__device__ __forceinline__ void ds_for_blocks(const K* __restrict__ keys, int64_t i0, int64_t i1, const K* top,
+                                              int nt, KeyMap<K> map, F f) {
+  for (int64_t base = i0 + threadIdx.x; base < i1; base += (int64_t)kDsUnroll * kDsThreads) {
+    K x[kDsUnroll];
+    int h[kDsUnroll];
+#pragma unroll
+    for (int u = 0; u < kDsUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * kDsThreads;
+      x[u] = i < i1 ? keys[i] : K(0);
+    }
+    // the searches step by step side by side (ds_top for each key)
+    K e[kDsUnroll];
+#pragma unroll
+    for (int u = 0; u < kDsUnroll; ++u) {
+      e[u] = map.enc(x[u]);
+      h[u] = 0;
+    }
+    for (int step = ds_pow2_floor(nt); step >= 1; step >>= 1) {
+#pragma unroll
+      for (int u = 0; u < kDsUnroll; ++u)
+        if (h[u] + step <= nt && top[h[u] + step - 1] < e[u]) h[u] += step;
+    }
+#pragma unroll
+    for (int u = 0; u < kDsUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * kDsThreads;
+      if (i < i1) f(i, x[u], h[u]);
+    }
+  }
+}
+
+// hist[h] = keys of this work-group's chunk in block h (nt + 1 entries)
+template <class K>
+__device__ __forceinline__ void ds_block_hist(const K* __restrict__ keys, int64_t i0, int64_t i1, const K* top,
+                                              int nt, uint32_t* hist, KeyMap<K> map) {
+  for (int h = threadIdx.x; h <= nt; h += kDsThreads) hist[h] = 0;
+  __syncthreads();
+  ds_for_blocks(keys, i0, i1, top, nt, map, [&](int64_t, K, int h) { atomicAdd(&hist[h], 1u); });
+  __syncthreads();
+}
+
+template <class K>
+__global__ void __launch_bounds__(kDsThreads)
+ds_block_count_kernel(const K* __restrict__ keys, int64_t n, const K* __restrict__ spl, int nspl,
+                      uint32_t* __restrict__ block_count, KeyMap<K> map) {
+  __shared__ K top[kDsTop];
+  __shared__ uint32_t hist[kDsTop + 1];
+  const int nt = ds_load_top(top, spl, nspl);
+  int64_t i0, i1;
+  ds_chunk(n, i0, i1);
+  ds_block_hist(keys, i0, i1, top, nt, hist, map);
+  for (int h = threadIdx.x; h <= nt; h += kDsThreads)
+    if (hist[h]) atomicAdd(&block_count[h], hist[h]);
+}
+
+// One work-group: block_off[0..nb] = exclusive scan of block_count[0..nb),
+// block_cursor = block_off (nb <= kDsTop + 1).
+__global__ void __launch_bounds__(1024)
+ds_block_scan_kernel(const uint32_t* __restrict__ block_count, int nb, uint32_t* __restrict__ block_off,
+                     uint32_t* __restrict__ block_cursor) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (nb + 1023) / 1024;
+  const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+  uint32_t sum = 0;
+  for (int b = b0; b < b1; ++b) sum += block_count[b];
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint32_t y = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += y;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (int b = b0; b < b1; ++b) {
+    block_off[b] = run;
+    block_cursor[b] = run;
+    run += block_count[b];
+  }
+  if (t == 1023) block_off[nb] = part[1023];
+}
+
+// Keys (and payloads) of each chunk to their blocks' ranges in the temporary
+// buffer: the work-group reserves one range per block with one atomic, then
+// each key takes the next slot of its block's range (an LDS atomic).
+template <class K, int V>
+__global__ void __launch_bounds__(kDsThreads)
+ds_block_scatter_kernel(const K* __restrict__ keys, const Pay<V>* __restrict__ vals, int64_t n,
+                        const K* __restrict__ spl, int nspl, uint32_t* __restrict__ block_cursor,
+                        K* __restrict__ out_keys, Pay<V>* __restrict__ out_vals, KeyMap<K> map) {
+  __shared__ K top[kDsTop];
+  __shared__ uint32_t hist[kDsTop + 1];
+  const int nt = ds_load_top(top, spl, nspl);
+  int64_t i0, i1;
+  ds_chunk(n, i0, i1);
+  ds_block_hist(keys, i0, i1, top, nt, hist, map);
+  for (int h = threadIdx.x; h <= nt; h += kDsThreads)
+    if (hist[h]) hist[h] = atomicAdd(&block_cursor[h], hist[h]);
+  __syncthreads();
+  ds_for_blocks(keys, i0, i1, top, nt, map, [&](int64_t i, K x, int h) {
+    const uint32_t pos = atomicAdd(&hist[h], 1u);
+    out_keys[pos] = x;
+    if constexpr (V) out_vals[pos] = vals[i];
+  });
+}
+
+// Work-group h: the keys of block h (block_off[h] .. block_off[h + 1] of the
+// temporary buffer) to their buckets in keys/vals; writes offsets[b] for the
+// block's buckets (and offsets[nb] = n) and lists its range buckets above
+// kDsBaseN keys.
+template <class K, int V>
+__global__ void __launch_bounds__(kDsThreads)
+ds_block_bucket_kernel(const K* __restrict__ tk, const Pay<V>* __restrict__ tv, const K* __restrict__ spl, int nspl,
+                       const uint32_t* __restrict__ block_off, K* __restrict__ keys, Pay<V>* __restrict__ vals,
+                       int32_t* __restrict__ offsets, int nb, uint32_t* __restrict__ big,
+                       uint32_t* __restrict__ nbig, KeyMap<K> map) {
+  __shared__ K bs[kDsBlock];
+  __shared__ uint32_t cnt[2 * kDsBlock];
+  __shared__ uint32_t part[kDsThreads];
+  const int nt = (nspl + kDsBlock - 1) / kDsBlock;
+  const int h = blockIdx.x;
+  const int j0 = h * kDsBlock;
+  const int len = h < nt ? min(kDsBlock, nspl - j0) : 0;
+  const int nloc = h < nt ? 2 * len : 1;  // buckets of this block
+  const int b0 = h < nt ? 2 * j0 : nb - 1;
+  const uint32_t lo = block_off[h], hi = block_off[h + 1];
+  for (int t = threadIdx.x; t < len; t += kDsThreads) bs[t] = spl[j0 + t];  // splitters are stored as words
+  for (int t = threadIdx.x; t < 2 * kDsBlock; t += kDsThreads) cnt[t] = 0;
+  __syncthreads();
+  // f(i, key, local bucket) for the block's keys: local bucket 2r or 2r + 1,
+  // r = #{block splitters < e} (< len, see above); kDsUnroll keys per thread
+  // at a time, so that their searches overlap
+  auto for_local = [&](auto f) __attribute__((always_inline)) {
+    for (uint32_t base = lo + threadIdx.x; base < hi; base += kDsUnroll * kDsThreads) {
+      K x[kDsUnroll];
+      int lb[kDsUnroll];
+#pragma unroll
+      for (int u = 0; u < kDsUnroll; ++u) {
+        const uint32_t i = base + u * kDsThreads;
+        x[u] = i < hi ? tk[i] : K(0);
+      }
+      // the searches step by step side by side (local for each key)
+      K e[kDsUnroll];
+      int r[kDsUnroll];
+#pragma unroll
+      for (int u = 0; u < kDsUnroll; ++u) {
+        e[u] = map.enc(x[u]);
+        r[u] = 0;
+      }
+#pragma unroll
+      for (int step = kDsBlock / 2; step >= 1; step >>= 1) {
+#pragma unroll
+        for (int u = 0; u < kDsUnroll; ++u)
+          if (r[u] + step <= len && bs[r[u] + step - 1] < e[u]) r[u] += step;
+      }
+#pragma unroll
+      for (int u = 0; u < kDsUnroll; ++u) {
+        const int q = max(0, min(r[u], len - 1));  // (r < len already for every key of the block)
+        lb[u] = len == 0 ? 0 : 2 * q + (bs[q] == e[u] ? 1 : 0);
+      }
+#pragma unroll
+      for (int u = 0; u < kDsUnroll; ++u) {
+        const uint32_t i = base + u * kDsThreads;
+        if (i < hi) f(i, x[u], lb[u]);
+      }
+    }
+  };
+  for_local([&](uint32_t, K, int b) { atomicAdd(&cnt[b], 1u); });
+  __syncthreads();
+  // exclusive scan of cnt[0 .. 2 kDsBlock): two entries per thread
+  const int t = threadIdx.x;
+  const uint32_t c0 = cnt[2 * t], c1 = cnt[2 * t + 1];
+  part[t] = c0 + c1;
+  __syncthreads();
+  for (int d = 1; d < kDsThreads; d <<= 1) {
+    const uint32_t y = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += y;
+    __syncthreads();
+  }
+  const uint32_t e0 = part[t] - c0 - c1;
+  __syncthreads();  // every count is read before the cursors overwrite them
+  const uint32_t starts[2] = {e0, e0 + c0}, counts[2] = {c0, c1};
+  for (int q = 0; q < 2; ++q) {
+    const int lb = 2 * t + q;
+    if (lb < nloc) {
+      const int b = b0 + lb;
+      offsets[b] = (int32_t)(lo + starts[q]);
+      if ((b & 1) == 0 && counts[q] > (uint32_t)kDsBaseN) big[atomicAdd(nbig, 1u)] = (uint32_t)b;
+    }
+    cnt[lb] = starts[q];
+  }
+  if (h == nt && t == 0) offsets[nb] = (int32_t)hi;
+  __syncthreads();
+  for_local([&](uint32_t i, K x, int b) {
+    const uint32_t pos = lo + atomicAdd(&cnt[b], 1u);
+    keys[pos] = x;
+    if constexpr (V) vals[pos] = tv[i];
+  });
+}
+
 template <class K, int V>
 __global__ void __launch_bounds__(kDsThreads)
 ds_copy_kernel(K* __restrict__ dk, Pay<V>* __restrict__ dv, const K* __restrict__ sk, const Pay<V>* __restrict__ sv,
@@ -196,6 +435,7 @@ static size_t ds_level_bytes(int64_t n, size_t ksz) {
   b += ds_align((size_t)p.nspl * ksz);                                       // splitters
   b += 3 * ds_align((size_t)(p.nb + 1) * 4);                                 // counts, offsets, cursors
   b += ds_align((size_t)(p.nb + 1) * 4) + 256;                               // big-bucket list + count
+  b += 3 * ds_align((size_t)(kDsTop + 2) * 4);                               // block counts, offsets, cursors
   b += ds_align((size_t)p.nb * 4) + ds_align(kSegCtrlBytes) + ds_align(kSegHistBytes);  // segmented-sort buffers
   b += ds_align((size_t)p.s * ksz) + ds_level_bytes(p.s, ksz);              // sorting the sample
   return b;
@@ -277,6 +517,9 @@ static hipError_t ds_sort(DeviceCtx* c, K* keys, Pay<V>* vals, int64_t n, K* tmp
   auto* cursors = static_cast<uint32_t*>(cv.take((size_t)(p.nb + 1) * 4));
   auto* big = static_cast<uint32_t*>(cv.take((size_t)(p.nb + 1) * 4));
   auto* nbig = static_cast<uint32_t*>(cv.take(256));
+  auto* block_count = static_cast<uint32_t*>(cv.take((size_t)(kDsTop + 2) * 4));
+  auto* block_off = static_cast<uint32_t*>(cv.take((size_t)(kDsTop + 2) * 4));
+  auto* block_cursor = static_cast<uint32_t*>(cv.take((size_t)(kDsTop + 2) * 4));
   SegBuffers b;
   b.ids = static_cast<int32_t*>(cv.take((size_t)p.nb * 4));
   b.ctrl = static_cast<uint32_t*>(cv.take(kSegCtrlBytes));
@@ -296,21 +539,42 @@ static hipError_t ds_sort(DeviceCtx* c, K* keys, Pay<V>* vals, int64_t n, K* tmp
   hipLaunchKernelGGL(ds_splitter_kernel<K>, dim3(ds_grid(c, p.nspl)), dim3(kDsThreads), 0, s, sample, spl, p.nspl,
                      map);
 
-  // count, scan, scatter into the temporary buffer
-  e = hipMemsetAsync(counts, 0, (size_t)(p.nb + 1) * 4, s);
-  if (e == hipSuccess) e = hipMemsetAsync(nbig, 0, 4, s);
+  // Two-pass partition: the buckets end in keys/vals, sorted there; the
+  // single-pass one leaves them in the temporary buffer.
+  const int nt = (p.nspl + kDsBlock - 1) / kDsBlock;
+  const bool two_pass = nt > kDsTwoPassBlocks;
+  K* bk = two_pass ? keys : tmp_keys;  // where the buckets are sorted
+  Pay<V>* bv = two_pass ? vals : tmp_vals;
+  K* ok = two_pass ? tmp_keys : keys;  // the other buffer: temporary of the recursion
+  Pay<V>* ov = two_pass ? tmp_vals : vals;
+  e = hipMemsetAsync(nbig, 0, 4, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ds_count_kernel<K>, dim3(g), dim3(kDsThreads), 0, s, keys, n, spl, p.nspl, counts, map);
-  hipLaunchKernelGGL(ds_scan_kernel, dim3(1), dim3(1024), 0, s, counts, p.nb, offsets, cursors, big, nbig);
-  hipLaunchKernelGGL((ds_scatter_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, n, spl, p.nspl,
-                     cursors, tmp_keys, tmp_vals, map);
+  if (two_pass) {
+    e = hipMemsetAsync(block_count, 0, (size_t)(nt + 1) * 4, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ds_block_count_kernel<K>, dim3(g), dim3(kDsThreads), 0, s, keys, n, spl, p.nspl, block_count,
+                       map);
+    hipLaunchKernelGGL(ds_block_scan_kernel, dim3(1), dim3(1024), 0, s, block_count, nt + 1, block_off, block_cursor);
+    hipLaunchKernelGGL((ds_block_scatter_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, n, spl, p.nspl,
+                       block_cursor, tmp_keys, tmp_vals, map);
+    hipLaunchKernelGGL((ds_block_bucket_kernel<K, V>), dim3(nt + 1), dim3(kDsThreads), 0, s, tmp_keys, tmp_vals, spl,
+                       p.nspl, block_off, keys, vals, offsets, p.nb, big, nbig, map);
+  } else {
+    // count, scan, scatter into the temporary buffer
+    e = hipMemsetAsync(counts, 0, (size_t)(p.nb + 1) * 4, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ds_count_kernel<K>, dim3(g), dim3(kDsThreads), 0, s, keys, n, spl, p.nspl, counts, map);
+    hipLaunchKernelGGL(ds_scan_kernel, dim3(1), dim3(1024), 0, s, counts, p.nb, offsets, cursors, big, nbig);
+    hipLaunchKernelGGL((ds_scatter_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, n, spl, p.nspl,
+                       cursors, tmp_keys, tmp_vals, map);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
   // the buckets of at most 4096 keys: one segmented sort (larger ones are skipped)
-  if (ds_segmented<K>(c, b, tmp_keys, tmp_vals, V, offsets, p.nb, map, s) != 0) return hipErrorUnknown;
+  if (ds_segmented<K>(c, b, bk, bv, V, offsets, p.nb, map, s) != 0) return hipErrorUnknown;
 
-  // range buckets above 4096 keys: the same sort, with keys/vals (now free) as temporary
+  // range buckets above 4096 keys: the same sort, with the other buffer (now free) as temporary
   uint32_t nb_host = 0;
   e = hipMemcpyAsync(&nb_host, nbig, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -324,12 +588,13 @@ static hipError_t ds_sort(DeviceCtx* c, K* keys, Pay<V>* vals, int64_t n, K* tmp
     if (e != hipSuccess) return e;
     for (uint32_t bi : bigs) {
       const int64_t lo = offs[bi], m = (int64_t)offs[bi + 1] - offs[bi];
-      e = ds_sort<K, V>(c, tmp_keys + lo, V ? tmp_vals + lo : nullptr, m, keys + lo, V ? vals + lo : nullptr,
-                        ws, ws_end, map, s, depth + 1);
+      e = ds_sort<K, V>(c, bk + lo, V ? bv + lo : nullptr, m, ok + lo, V ? ov + lo : nullptr, ws, ws_end, map, s,
+                        depth + 1);
       if (e != hipSuccess) return e;
     }
   }
-  hipLaunchKernelGGL((ds_copy_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, tmp_keys, tmp_vals, n);
+  if (!two_pass)
+    hipLaunchKernelGGL((ds_copy_kernel<K, V>), dim3(g), dim3(kDsThreads), 0, s, keys, vals, tmp_keys, tmp_vals, n);
   return hipGetLastError();
 }
 

@@ -1,6 +1,8 @@
 """Parity of the device-wide sort (sample-sort partitions with the small
 sorters as base case) with the CPU oracle: every key type, payloads, skewed
-and duplicate-heavy inputs, sizes around every threshold."""
+and duplicate-heavy inputs, sizes around every threshold (from about two
+million keys a level partitions in two passes, by splitter block and then by
+bucket; below, in one)."""
 import ctypes
 
 import numpy as np
@@ -13,7 +15,7 @@ from helpers import first_mismatch, from_dev, to_dev
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [0, 1, 2, 17, 300, 4096, 4097, 10_001, 70_000, 1_000_003]
+SIZES = [0, 1, 2, 17, 300, 4096, 4097, 10_001, 70_000, 1_000_003, 2_500_000, 9_000_001]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -51,9 +53,9 @@ def test_device_sort_keys(dtype):
         assert (bits(got) == bits(want)).all(), f"n={n}: {first_mismatch(bits(got), bits(want))}"
 
 
+@pytest.mark.parametrize("n", [600_000, 3_000_000])
 @pytest.mark.parametrize("kind", ["all_equal", "few", "zipf", "sorted", "reverse", "one_heavy", "narrow"])
-def test_device_sort_skewed_inputs(kind):
-    n = 600_000
+def test_device_sort_skewed_inputs(kind, n):
     rng = np.random.default_rng(3)
     if kind == "all_equal":
         a = np.full(n, 77, np.uint32)
@@ -69,7 +71,7 @@ def test_device_sort_skewed_inputs(kind):
         a = inputs.random_keys(np.uint32, n, 6)
         a[rng.random(n) < 0.7] = 123456
     else:  # values in a narrow band: many buckets of one value, many range buckets
-        a = rng.integers(1000, 1000 + 50_000, size=n).astype(np.uint32)
+        a = rng.integers(1000, 1000 + n // 12, size=n).astype(np.uint32)
     got, _ = run(a)
     want, _ = want_sorted(a)
     assert (got == want).all(), first_mismatch(got, want)
@@ -77,20 +79,21 @@ def test_device_sort_skewed_inputs(kind):
 
 @pytest.mark.parametrize("vb", [4, 8])
 def test_device_sort_payloads(vb):
-    for n in (5000, 250_000):
+    for n in (5000, 250_000, 3_000_000):
         keys = inputs.distinct_u64(n, seed=n + vb)
         vals = np.arange(n, dtype=np.uint32) if vb == 4 else inputs.splitmix64(9, n)
         gk, gv = run(keys, vals)
         wk, wv = want_sorted(keys, vals)
         assert (gk == wk).all() and (gv == wv).all()
     # duplicates with a payload: keys exact, pairs as a multiset
-    keys = inputs.random_keys(np.int64, 300_000, 10)
-    keys[np.random.default_rng(2).random(keys.size) < 0.5] = -3
-    vals = np.arange(keys.size, dtype=np.uint32)
-    gk, gv = run(keys, vals)
-    wk, _ = want_sorted(keys, vals)
-    assert (gk == wk).all()
-    assert (np.sort(gv) == vals).all() and (keys[gv] == gk).all()
+    for n in (300_000, 3_000_000):
+        keys = inputs.random_keys(np.int64, n, 10)
+        keys[np.random.default_rng(2).random(keys.size) < 0.5] = -3
+        vals = np.arange(keys.size, dtype=np.uint32)
+        gk, gv = run(keys, vals)
+        wk, _ = want_sorted(keys, vals)
+        assert (gk == wk).all()
+        assert (np.sort(gv) == vals).all() and (keys[gv] == gk).all()
 
 
 def test_device_sort_workspace_and_argument_errors():
