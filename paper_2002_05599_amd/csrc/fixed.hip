@@ -228,8 +228,9 @@ fixed_half_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
 // so every thread loads its chunks straight from HBM (consecutive lanes,
 // consecutive chunks: fully coalesced), sorts them in registers and stores
 // them back; no LDS staging.  (For 16-byte arrays the staged tile measured
-// faster.)
-constexpr int kVecChunks = 4;  // chunks per thread in flight
+// faster.)  One chunk per thread: on 2^24 arrays 1, 2, 4 and 8 chunks per
+// thread measured 0.77, 0.755, 0.71-0.72 and 0.70 of 8 TB/s.
+constexpr int kVecChunks = 1;  // chunks per thread
 template <int F, int N, class K>
 __global__ void __launch_bounds__(kTileThreads)
 fixed_vec_kernel(K* __restrict__ keys, int64_t chunks, KeyMap<K> flip) {
