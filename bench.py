@@ -64,9 +64,25 @@ def parse():
 # --- counters --------------------------------------------------------------------
 
 # source files that define each profiled kernel's device code
+_FIXED_SOURCES = ("fixed.hip", "common.hpp", "keymap.hpp", "networks_gen.hpp")
 KERNEL_SOURCES = {
-    "fixed_tile_kernel<n=16,u32>": ("fixed.hip", "common.hpp", "keymap.hpp", "networks_gen.hpp"),
+    "fixed_tile_kernel<n=16,u32>": _FIXED_SOURCES,
+    "fixed_half_tile_kernel<n=16,u32>": _FIXED_SOURCES,
+    "fixed_wide_tile_kernel<n=16,u32>": _FIXED_SOURCES,
 }
+
+
+def fixed16_kernel(ss):
+    """The kernel that sorts 16-key uint32 arrays under the current tuning
+    (the tile form chosen for n = 16)."""
+    apt = ss.get_tuning("u32.fixed_apt")
+    if apt >= 2:  # tiles of several arrays per thread (no counter record is kept for them)
+        return f"fixed_tile_kernel<n=16,u32,{apt} arrays per thread>"
+    if (ss.get_tuning("u32.fixed_wide") >> 16) & 1:
+        return "fixed_wide_tile_kernel<n=16,u32>"
+    if (ss.get_tuning("u32.fixed_half") >> 16) & 1:
+        return "fixed_half_tile_kernel<n=16,u32>"
+    return "fixed_tile_kernel<n=16,u32>"
 
 
 def kernel_source_hash(kernel_key):
@@ -84,6 +100,8 @@ def traffic_for(kernel_key, family):
     try:
         data = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
     except (OSError, ValueError):
+        return None
+    if kernel_key not in KERNEL_SOURCES:
         return None
     ent = data.get(kernel_key, {}).get(f"family {family}")
     if not ent or ent.get("source_hash") != kernel_source_hash(kernel_key):
@@ -166,7 +184,7 @@ def bench_fixed16(args):
     nkeys = count * n
     algo_bytes = 2 * nkeys * 4
     achieved = algo_bytes / (ms * 1e-3) / 1e9
-    kkey = "fixed_tile_kernel<n=16,u32>"
+    kkey = fixed16_kernel(ss)
     family = ss.get_tuning("u32.family")
     del bufs, keys
     torch.cuda.empty_cache()

@@ -211,7 +211,7 @@ const char *ss_strerror(ss_status status);
 
 /*
  * Tuning parameters (variant choices found by the autotuner).  The first
- * eleven are kept per key width: "<name>" sets both widths, "u32.<name>" or
+ * twelve are kept per key width: "<name>" sets both widths, "u32.<name>" or
  * "u64.<name>" one of them (32-bit keys: uint32, int32, float; 64-bit keys:
  * uint64, int64, double); getting "<name>" returns -2 when the widths differ.
  *   "family"       n <= 16: 0 = fewest-comparator networks, 1 = Bose-Nelson
@@ -234,6 +234,10 @@ const char *ss_strerror(ss_status status);
  *                  where one array per thread is used, arrays of n keys are
  *                  staged by 128-thread work-groups (half the LDS tile of the
  *                  256-thread form)
+ *   "fixed_wide"   same form of mask: arrays of n keys are staged by
+ *                  512-thread work-groups over tiles of 256 arrays (each
+ *                  thread moves half as many chunks); takes precedence over
+ *                  "fixed_half"
  *   "rss_finish"   how Register Sample Sort finishes its buckets of 2..16
  *                  keys: 0 = one network per bucket (Section 3, default),
  *                  1 = rank counting (each key counts the smaller keys of its

@@ -11,10 +11,11 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
   fixed_apt        arrays per thread of the fixed-layout kernels (items per
                    thread; fixed arrays of 2..16 keys: it applies wherever the
                    tile of several arrays per thread fits)
-  fixed_half       per n = 2..16, whether the one-array-per-thread tile of
-                   arrays of n keys is staged by 128 or by 256 threads (each
-                   bit tuned on its own fixed batch of that n, back-to-back
-                   calls, the two forms alternating)
+  fixed_half, fixed_wide
+                   per n = 2..16, whether the one-array-per-thread tile of
+                   arrays of n keys is staged by 256 threads, by 128, or by
+                   512 threads over 256 arrays (each n tuned on its own fixed
+                   batch of that n, back-to-back calls, the forms alternating)
   rss_bound_tiny, rss_bound_small, rss_bound_mid
                    the wave-to-segment mapping: which segment sizes get 8, 16,
                    32 or 64 lanes (CSR batches of 17..256, 17..64 and 65..128
@@ -206,19 +207,21 @@ def candidates(name):
             "persist_split": [0, 1], "net_mix": [0, 1], "interleave": [0, 1], "persist_occ": [0, 1, 2, 3]}[name]
 
 
-def _tune_half(name, width, quick, reps, log):
-    """The bit mask of n whose one-array-per-thread tile uses 128 threads.  For
-    each n the two forms are compared on one fixed batch of that n (2^24
-    arrays and at least 512 MB, so that the Infinity Cache cannot hold it; a
-    quarter in quick mode) with the other bits as chosen so far: the networks
-    are data-oblivious, so each sample times 8 back-to-back in-place calls,
-    and `reps` samples of the two forms alternate so that drift affects both
+def _tune_tile_threads(width, quick, reps, log):
+    """Per n, the work-group size of the one-array-per-thread tile: 256 threads
+    (neither bit), 128 (bit n of fixed_half) or 512 over 256 arrays (bit n of
+    fixed_wide).  For each n the forms are compared on one fixed batch of that
+    n (2^24 arrays and at least 512 MB, so that the Infinity Cache cannot hold
+    it; a quarter in quick mode) with the other n as chosen so far: the
+    networks are data-oblivious, so each sample times 8 back-to-back in-place
+    calls, and `reps` samples of the forms alternate so that drift affects all
     alike.  Each form's output is checked against the library's default."""
     import torch
     from . import get_tuning, set_tuning
     d = 4 if quick else 1
     kb = 4 if width == "u32" else 8
-    mask = get_tuning(name)
+    hn, wn = f"{width}.fixed_half", f"{width}.fixed_wide"
+    half, wide = get_tuning(hn), get_tuning(wn)
     results, rejected = {}, []
     stream = torch.cuda.current_stream()
 
@@ -232,43 +235,49 @@ def _tune_half(name, width, quick, reps, log):
         e1.synchronize()
         return e0.elapsed_time(e1) / 8
 
+    def apply(form, n):
+        set_tuning(hn, (half & ~(1 << n)) | ((1 if form == 128 else 0) << n))
+        set_tuning(wn, (wide & ~(1 << n)) | ((1 if form == 512 else 0) << n))
+
     for n in range(2, 17):
         count = max(1 << 24, (1 << 29) // (n * kb)) // d
         case = _fixed_case(width, n, count, n)
-        forms = {bit: (mask & ~(1 << n)) | (bit << n) for bit in (0, 1)}
-        set_tuning(name, forms[0])
+        apply(256, n)
         case.record_reference()
         valid = []
-        for bit in (0, 1):
-            set_tuning(name, forms[bit])
+        for form in (256, 128, 512):
+            apply(form, n)
             case.restore()
             case.call(case.bufs)
             if case.output_matches():
-                valid.append(bit)
+                valid.append(form)
             else:
-                rejected.append(f"n={n} bit={bit}")
-                log(f"  {name} n={n} bit={bit}: output differs from the reference -- rejected")
-        samples = {bit: [] for bit in valid}
+                rejected.append(f"n={n} threads={form}")
+                log(f"  tile threads n={n} {form}: output differs from the reference -- rejected")
+        samples = {form: [] for form in valid}
         for _ in range(reps):
-            for bit in valid:
-                set_tuning(name, forms[bit])
-                samples[bit].append(sample(case))
-        times = {bit: float(np.median(v)) for bit, v in samples.items()}
-        for bit, ms in times.items():
-            log(f"  {name} n={n} threads={128 if bit else 256}: {ms:.4f} ms  "
-                f"{case.nbytes / (ms * 1e-3) / 1e9:.1f} GB/s")
-        cur = (mask >> n) & 1
+            for form in valid:
+                apply(form, n)
+                samples[form].append(sample(case))
+        times = {form: float(np.median(v)) for form, v in samples.items()}
+        for form, ms in times.items():
+            log(f"  {width} tile n={n} threads={form}: {ms:.4f} ms  {case.nbytes / (ms * 1e-3) / 1e9:.1f} GB/s")
+        cur = 512 if (wide >> n) & 1 else (128 if (half >> n) & 1 else 256)  # wide takes precedence
         pick = min(times, key=times.get) if times else cur
         if cur in times and times[pick] > (1.0 - NOISE) * times[cur]:
             pick = cur
-        mask = forms[pick]
-        results[f"n={n}"] = {"arrays": count, "ms_256": times.get(0), "ms_128": times.get(1),
-                             "threads": 128 if pick else 256}
+        half = (half & ~(1 << n)) | ((1 if pick == 128 else 0) << n)
+        wide = (wide & ~(1 << n)) | ((1 if pick == 512 else 0) << n)
+        apply(pick, n)
+        results[f"n={n}"] = {"arrays": count, "ms_256": times.get(256), "ms_128": times.get(128),
+                             "ms_512": times.get(512), "threads": pick}
         del case
         torch.cuda.empty_cache()
-    set_tuning(name, mask)
-    log(f"{name} -> {mask:#x}")
-    return mask, {"workloads": [f"{width} fixed n=2..16"], "results": results, "rejected": rejected, "best": mask}
+    set_tuning(hn, half)
+    set_tuning(wn, wide)
+    log(f"{hn} -> {half:#x}, {wn} -> {wide:#x}")
+    return {hn: half, wn: wide}, {"workloads": [f"{width} fixed n=2..16"], "results": results,
+                                  "rejected": rejected, "best": {"fixed_half": half, "fixed_wide": wide}}
 
 
 def tune(quick=False, reps=5, log=print):
@@ -281,8 +290,9 @@ def tune(quick=False, reps=5, log=print):
     order = [(wd, k) for wd in ("u32", "u64") for k in PER_WIDTH] + [("all", k) for k in GLOBAL]
     for width, knob in order:
         name = knob if width == "all" else f"{width}.{knob}"
-        if knob == "fixed_half":
-            best[name], report[name] = _tune_half(name, width, quick, reps, log)
+        if knob == "fixed_half":  # with fixed_wide: one choice per n among three tile forms
+            masks, report[f"{width}.tile_threads"] = _tune_tile_threads(width, quick, reps, log)
+            best.update(masks)
             continue
         current = get_tuning(name)
         cases = w.cases[(width, knob)]

@@ -82,11 +82,12 @@ template <class K> __device__ __forceinline__ void lds_st(unsigned char* p, K v)
   *reinterpret_cast<K*>(p) = v;
 }
 
-// One tile of TT threads (256, or 128 for a one-array-per-thread tile of half
-// the LDS).
-template <int F, int N, class K, int A, int TT>
+// One tile of A * TS arrays moved by TT threads (TT = TS = 256; 128 for a
+// one-array-per-thread tile of half the LDS; TT = 512 over TS = 256 arrays,
+// where every thread moves half as many chunks and the first 256 sort).
+template <int F, int N, class K, int A, int TT, int TS = TT>
 __device__ __forceinline__ void tile_sort(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
-  using L = TileLayout<N, K, A, TT>;
+  using L = TileLayout<N, K, A, TS>;
   constexpr int TA = L::TA;
   __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
   constexpr int kChunks = TA * N * L::E / 16;  // 16-byte chunks in a full tile
@@ -140,7 +141,7 @@ __device__ __forceinline__ void tile_sort(K* __restrict__ keys, int64_t count, K
 
 #pragma unroll
   for (int q = 0; q < A; ++q) {
-    const int a = t + q * TT;  // this thread's q-th array of the tile
+    const int a = t + q * TS;  // this thread's q-th array of the tile (none for t >= TS)
     if (a < valid) {
       K r[N];
       if constexpr (L::kVec) {
@@ -224,6 +225,16 @@ fixed_half_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
   tile_sort<F, N, K, 1, kHalfTileThreads>(keys, count, flip);
 }
 
+// The one-array-per-thread tile of 256 arrays moved by 512 threads: each
+// thread loads and stores half as many 16-byte chunks, the first 256 threads
+// sort.
+constexpr int kWideTileThreads = 512;
+template <int F, int N, class K>
+__global__ void __launch_bounds__(kWideTileThreads)
+fixed_wide_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
+  tile_sort<F, N, K, 1, kWideTileThreads, kTileThreads>(keys, count, flip);
+}
+
 // Arrays of 8 bytes (uint32 n = 2): a 16-byte chunk holds two whole arrays,
 // so every thread loads its chunks straight from HBM (consecutive lanes,
 // consecutive chunks: fully coalesced), sorts them in registers and stores
@@ -285,12 +296,15 @@ fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, KeyMap<
 
 template <int F, int N, class K, int A, int TT = kTileThreads>
 static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_t s) {
-  constexpr int64_t TA = (int64_t)A * TT;
+  constexpr int64_t TA = (int64_t)A * (TT == kWideTileThreads ? kTileThreads : TT);  // arrays per work-group
   const int64_t blocks = (count + TA - 1) / TA;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   if constexpr (TT == kHalfTileThreads) {
     static_assert(A == 1, "the 128-thread tile holds one array per thread");
     hipLaunchKernelGGL((fixed_half_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
+  } else if constexpr (TT == kWideTileThreads) {
+    static_assert(A == 1, "the 512-thread tile holds 256 arrays");
+    hipLaunchKernelGGL((fixed_wide_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
   } else {
     hipLaunchKernelGGL((fixed_tile_kernel<F, N, K, A>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
   }
@@ -299,7 +313,7 @@ static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_
 
 template <int F, int N, class K>
 static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, int apt, bool half,
-                                 hipStream_t s) {
+                                 bool wide, hipStream_t s) {
   const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
@@ -327,6 +341,7 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<
     if constexpr (tile_fits<N, K, 2>()) {
       if (apt >= 2) return launch_tile<F, N, K, 2>(keys, count, flip, s);
     }
+    if (wide) return launch_tile<F, N, K, 1, kWideTileThreads>(keys, count, flip, s);
     if (half) return launch_tile<F, N, K, 1, kHalfTileThreads>(keys, count, flip, s);
     return launch_tile<F, N, K, 1>(keys, count, flip, s);
   } else {
@@ -341,30 +356,32 @@ static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, 
   const Tuning t = tuning(sizeof(K));
   const int apt = t.fixed_apt;
   const bool half = ((t.fixed_half >> n) & 1) != 0;
+  const bool wide = ((t.fixed_wide >> n) & 1) != 0;
   switch (n) {
-    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, half, s);
-    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, half, s);
-    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, half, s);
-    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, half, s);
-    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, half, s);
-    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, half, s);
-    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, half, s);
-    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, half, s);
-    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, half, s);
-    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, half, s);
-    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, half, s);
-    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, half, s);
-    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, half, s);
-    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, half, s);
-    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, half, s);
+    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, half, wide, s);
+    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, half, wide, s);
+    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, half, wide, s);
+    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, half, wide, s);
+    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, half, wide, s);
+    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, half, wide, s);
+    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, half, wide, s);
+    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, half, wide, s);
+    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, half, wide, s);
+    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, half, wide, s);
+    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, half, wide, s);
+    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, half, wide, s);
+    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, half, wide, s);
+    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, half, wide, s);
+    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, half, wide, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // Streaming copy with the tile kernels' access pattern: each thread moves
 // 16-byte chunks with nontemporal loads and stores, consecutive lanes on
-// consecutive chunks, kCopyIters chunks per thread in flight.
-constexpr int kCopyIters = 4;
+// consecutive chunks, kCopyIters chunks per thread (on 1 GiB, 1, 2 and 4
+// chunks per thread measured 0.81, 0.76 and 0.78 of 8 TB/s).
+constexpr int kCopyIters = 1;
 __global__ void __launch_bounds__(kTileThreads)
 stream_copy_kernel(u32x4* __restrict__ dst, const u32x4* __restrict__ src, int64_t chunks) {
   const int64_t base = (int64_t)blockIdx.x * (kTileThreads * kCopyIters) + threadIdx.x;
