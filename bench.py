@@ -203,7 +203,7 @@ def bench_fixed16(args):
 
 def cpu_share():
     """Host threads this process may use: its CPU affinity, capped at the CPU
-    share a one-GPU machine gives a job (16 threads)."""
+    share of a one-GPU job on the MI355X hosts (16 threads)."""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
