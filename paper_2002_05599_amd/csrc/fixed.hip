@@ -5,8 +5,9 @@
 // keys).  Arrays sit back to back in HBM (the ArrayInRow layout of
 // Section 4.1), so a thread's own keys are N*sizeof(K) contiguous bytes and a
 // direct per-thread load would touch a different 16-byte piece of many cache
-// lines per instruction.  Instead a 256-thread work-group stages its tile of
-// 256 arrays through LDS:
+// lines per instruction.  Instead a work-group stages its tile of arrays
+// through LDS (256 threads and arrays; per n, as tuned, 128 threads and
+// arrays, or 512 threads moving a tile of 256 arrays):
 //
 //   HBM --(16-byte coalesced loads, consecutive lanes -> consecutive bytes)--> VGPRs
 //       --(LDS write in a conflict-avoiding layout)--> LDS
@@ -20,7 +21,7 @@
 //   * element layout otherwise: array a occupies elements [a*P, a*P+N) with
 //     an odd pitch P (N or N+1), so a wave's per-thread element reads hit
 //     distinct banks.
-// The last, partial tile (count not a multiple of 256) takes element-wise
+// The last, partial tile (count not a multiple of the tile) takes element-wise
 // global accesses guarded by bounds.  A stride other than N, or a base pointer
 // that is not 16-byte aligned, uses the direct per-thread kernel instead.
 #include "common.hpp"
