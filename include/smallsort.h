@@ -158,9 +158,9 @@ ss_status segmented_sort_pairs_u64(uint64_t *keys, uint64_t *refs, const int32_t
  * One large array sorted on the device, with the small sorters as its base
  * case (the paper's use of them inside Quicksort and IPS4o, Sections 4.4 and
  * 4.6, and the batching of base cases by size proposed in Section 5): sample
- * sort partitions with about 1024 keys per bucket and equality buckets for
- * repeated splitters, then one segmented sort of every bucket; a bucket still
- * above 4096 keys is partitioned again.
+ * sort partitions with about 1536 (32-bit keys) or 1024 (64-bit keys) keys per
+ * bucket and equality buckets for repeated splitters, then one segmented sort
+ * of every bucket; a bucket still above 4096 keys is partitioned again.
  *   keys:  n keys of key_type (SS_KEY_*), sorted in place (ascending; same
  *          order as the other calls).  n: 0 .. 2^31 - 1.
  *   vals:  NULL with val_bytes = 0, or a payload of val_bytes = 4 or 8 (8: 64-bit
