@@ -191,7 +191,7 @@ __device__ __forceinline__ void ds_chunk(int64_t n, int64_t& i0, int64_t& i1) {
 
 // Calls f(i, key, block) for the keys i0 <= i < i1, kDsUnroll per thread at
 // a time: their searches are independent chains of LDS reads that overlap.
-constexpr int kDsUnroll = 8;
+constexpr int kDsUnroll = 16;  // (4: 4% slower, 8: 3% slower on 2^28 uint32 keys)
 template <class K, class F>
 __device__ __forceinline__ void ds_for_blocks(const K* __restrict__ keys, int64_t i0, int64_t i1, const K* top,
                                               int nt, KeyMap<K> map, F f) {
