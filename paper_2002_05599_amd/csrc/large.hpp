@@ -1,9 +1,10 @@
 // Arrays of 257..4096 keys: one 256-thread work-group per array.
 //
 // Section 5 names merge sort with merging networks as the way to build on the
-// small sorters for larger inputs.  Here the array is cut into runs of 256
-// keys (128 for arrays of at most 512 keys, so that all four waves have a
-// run); each wave sorts its runs with Register Sample Sort (the same G = 64
+// small sorters for larger inputs.  Here the array of m keys is cut into 4r
+// runs of equal length (r = ceil(m / 1024), the length rounded up to a
+// multiple of 8, at most 256 keys), so that each of the four waves sorts r
+// runs; each wave sorts its runs with Register Sample Sort (the same G = 64
 // group sort as the 129..256-key class), and the sorted runs are then merged
 // pairwise in LDS, doubling the run length each round (at most four rounds
 // for 4096 keys).  In a merge round every thread produces the same number P
@@ -26,8 +27,7 @@ namespace ss {
 
 constexpr int kLargeThreads = 256;
 constexpr int kMaxLargeN = 4096;
-constexpr int kRunN = 256;                               // keys per run (one G = 64 group)
-constexpr int kShortRunN = kRunN / 2;                    // keys per run for arrays of at most 2 kRunN
+constexpr int kRunN = 256;                               // most keys per run (one G = 64 group)
 constexpr int kMergePerMax = kMaxLargeN / kLargeThreads;  // merge outputs per thread at 4096 keys
 
 template <class K, int V> struct LargeLds {
@@ -93,11 +93,13 @@ __device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv
   const int lane = lane_id();
   auto* group = reinterpret_cast<GroupLds<K, V, 64>*>(lds + LL::kBufBytes) + wave;
 
-  // runs of 256 keys (128 for up to 512 keys, so that every wave has a run),
-  // run r by wave r mod 4
-  const int run = m <= 2 * kRunN ? kShortRunN : kRunN;
+  // 4 rr runs of at most kRunN keys, a multiple of 8 each (so that 2 run is a
+  // multiple of the merge's outputs per thread), run r by wave r mod 4
+  constexpr int kWaves = kLargeThreads / kWave;
+  const int rr = (m + kWaves * kRunN - 1) / (kWaves * kRunN);
+  const int run = (((m + kWaves * rr - 1) / (kWaves * rr)) + 7) & ~7;
   const int nruns = (m + run - 1) / run;
-  for (int r = wave; r < nruns; r += kLargeThreads / kWave) {
+  for (int r = wave; r < nruns; r += kWaves) {
     const int lo = r * run;
     const int len = min(run, m - lo);
     rss_group_load(*group, gk + lo, V ? gv + lo : nullptr, len, flip);
@@ -112,8 +114,8 @@ __device__ __forceinline__ void large_sort(unsigned char* lds, K* gk, Pay<V>* gv
   __syncthreads();
 
   // merge rounds: runs of length L in buffer `cur` -> runs of 2L in the other;
-  // P outputs per thread, a power of two that divides 2L (P = 2 while
-  // runs of 128 keys are merged, at most 16 once L >= 256)
+  // P outputs per thread, a power of two of at most 16, so that it divides 2L
+  // (a multiple of 16)
   const int per = m <= 512 ? 2 : (m <= 1024 ? 4 : (m <= 2048 ? 8 : kMergePerMax));
   int cur = 0;
   for (int L = run; L < m; L *= 2) {
