@@ -158,9 +158,9 @@ def test_device_sort_workspace_size(lib):
 def test_per_width_tuning(lib):
     """Per-width knobs: the plain name sets both widths, a prefixed name one;
     a plain get of differing widths reads -2; global knobs take no prefix;
-    the lane-group bounds stay ordered."""
+    the lane-group bounds stay ordered; the tile-form masks take bits 2..16."""
     from helpers import tuned
-    with tuned(family=1, rss_bound_small=64, rss_bound_mid=128):
+    with tuned(family=1, rss_bound_small=64, rss_bound_mid=128, fixed_half=0, fixed_wide=0):
         ss.set_tuning("u64.family", 0)
         assert ss.get_tuning("u32.family") == 1 and ss.get_tuning("u64.family") == 0
         assert ss.get_tuning("family") == -2
@@ -179,3 +179,10 @@ def test_per_width_tuning(lib):
             ss.set_tuning("rss_oversample", v)
         with pytest.raises(ss.SmallSortError):
             ss.set_tuning("rss_oversample", 5)
+        for knob in ("fixed_half", "fixed_wide"):
+            ss.set_tuning(f"u32.{knob}", 0x1FFFC)
+            ss.set_tuning(f"u64.{knob}", 1 << 16)
+            assert ss.get_tuning(f"u32.{knob}") == 0x1FFFC and ss.get_tuning(f"u64.{knob}") == 1 << 16
+            for bad in (1, 2, 0x20000):  # n = 0, 1 and 17 have no bit
+                with pytest.raises(ss.SmallSortError):
+                    ss.set_tuning(knob, bad)
