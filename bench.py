@@ -69,6 +69,7 @@ KERNEL_SOURCES = {
     "fixed_tile_kernel<n=16,u32>": _FIXED_SOURCES,
     "fixed_half_tile_kernel<n=16,u32>": _FIXED_SOURCES,
     "fixed_wide_tile_kernel<n=16,u32>": _FIXED_SOURCES,
+    "fixed_wider_tile_kernel<n=16,u32>": _FIXED_SOURCES,
 }
 
 
@@ -78,6 +79,8 @@ def fixed16_kernel(ss):
     apt = ss.get_tuning("u32.fixed_apt")
     if apt >= 2:  # tiles of several arrays per thread (no counter record is kept for them)
         return f"fixed_tile_kernel<n=16,u32,{apt} arrays per thread>"
+    if (ss.get_tuning("u32.fixed_wider") >> 16) & 1:
+        return "fixed_wider_tile_kernel<n=16,u32>"
     if (ss.get_tuning("u32.fixed_wide") >> 16) & 1:
         return "fixed_wide_tile_kernel<n=16,u32>"
     if (ss.get_tuning("u32.fixed_half") >> 16) & 1:

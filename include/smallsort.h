@@ -211,7 +211,7 @@ const char *ss_strerror(ss_status status);
 
 /*
  * Tuning parameters (variant choices found by the autotuner).  The first
- * twelve are kept per key width: "<name>" sets both widths, "u32.<name>" or
+ * thirteen are kept per key width: "<name>" sets both widths, "u32.<name>" or
  * "u64.<name>" one of them (32-bit keys: uint32, int32, float; 64-bit keys:
  * uint64, int64, double); getting "<name>" returns -2 when the widths differ.
  *   "family"       n <= 16: 0 = fewest-comparator networks, 1 = Bose-Nelson
@@ -238,6 +238,10 @@ const char *ss_strerror(ss_status status);
  *                  512-thread work-groups over tiles of 256 arrays (each
  *                  thread moves half as many chunks); takes precedence over
  *                  "fixed_half"
+ *   "fixed_wider"  same, with 1024-thread work-groups (a quarter of the
+ *                  chunks per thread); takes precedence over both.  The two
+ *                  wide forms apply to the network families only (with
+ *                  family 2, insertion sort, their bits are ignored)
  *   "rss_finish"   how Register Sample Sort finishes its buckets of 2..16
  *                  keys: 0 = one network per bucket (Section 3, default),
  *                  1 = rank counting (each key counts the smaller keys of its

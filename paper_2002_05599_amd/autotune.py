@@ -11,11 +11,12 @@ Per key width (workloads of that width; 64-bit keys carry a uint32 payload):
   fixed_apt        arrays per thread of the fixed-layout kernels (items per
                    thread; fixed arrays of 2..16 keys: it applies wherever the
                    tile of several arrays per thread fits)
-  fixed_half, fixed_wide
+  fixed_half, fixed_wide, fixed_wider
                    per n = 2..16, whether the one-array-per-thread tile of
                    arrays of n keys is staged by 256 threads, by 128, or by
-                   512 threads over 256 arrays (each n tuned on its own fixed
-                   batch of that n, back-to-back calls, the forms alternating)
+                   512 or 1024 threads over 256 arrays (each n tuned on its
+                   own fixed batch of that n, back-to-back calls, the forms
+                   alternating)
   rss_bound_tiny, rss_bound_small, rss_bound_mid
                    the wave-to-segment mapping: which segment sizes get 8, 16,
                    32 or 64 lanes (CSR batches of 17..256, 17..64 and 65..128
@@ -209,8 +210,8 @@ def candidates(name):
 
 def _tune_tile_threads(width, quick, reps, log):
     """Per n, the work-group size of the one-array-per-thread tile: 256 threads
-    (neither bit), 128 (bit n of fixed_half) or 512 over 256 arrays (bit n of
-    fixed_wide).  For each n the forms are compared on one fixed batch of that
+    (no bit), 128 (bit n of fixed_half), 512 or 1024 over 256 arrays (bit n of
+    fixed_wide or fixed_wider).  For each n the forms are compared on one fixed batch of that
     n (2^24 arrays and at least 512 MB, so that the Infinity Cache cannot hold
     it; a quarter in quick mode) with the other n as chosen so far: the
     networks are data-oblivious, so each sample times 8 back-to-back in-place
@@ -220,8 +221,8 @@ def _tune_tile_threads(width, quick, reps, log):
     from . import get_tuning, set_tuning
     d = 4 if quick else 1
     kb = 4 if width == "u32" else 8
-    hn, wn = f"{width}.fixed_half", f"{width}.fixed_wide"
-    half, wide = get_tuning(hn), get_tuning(wn)
+    hn, wn, xn = f"{width}.fixed_half", f"{width}.fixed_wide", f"{width}.fixed_wider"
+    half, wide, wider = get_tuning(hn), get_tuning(wn), get_tuning(xn)
     results, rejected = {}, []
     stream = torch.cuda.current_stream()
 
@@ -238,6 +239,7 @@ def _tune_tile_threads(width, quick, reps, log):
     def apply(form, n):
         set_tuning(hn, (half & ~(1 << n)) | ((1 if form == 128 else 0) << n))
         set_tuning(wn, (wide & ~(1 << n)) | ((1 if form == 512 else 0) << n))
+        set_tuning(xn, (wider & ~(1 << n)) | ((1 if form == 1024 else 0) << n))
 
     for n in range(2, 17):
         count = max(1 << 24, (1 << 29) // (n * kb)) // d
@@ -245,7 +247,7 @@ def _tune_tile_threads(width, quick, reps, log):
         apply(256, n)
         case.record_reference()
         valid = []
-        for form in (256, 128, 512):
+        for form in (256, 128, 512, 1024):
             apply(form, n)
             case.restore()
             case.call(case.bufs)
@@ -262,22 +264,25 @@ def _tune_tile_threads(width, quick, reps, log):
         times = {form: float(np.median(v)) for form, v in samples.items()}
         for form, ms in times.items():
             log(f"  {width} tile n={n} threads={form}: {ms:.4f} ms  {case.nbytes / (ms * 1e-3) / 1e9:.1f} GB/s")
-        cur = 512 if (wide >> n) & 1 else (128 if (half >> n) & 1 else 256)  # wide takes precedence
+        cur = 1024 if (wider >> n) & 1 else (512 if (wide >> n) & 1 else (128 if (half >> n) & 1 else 256))
         pick = min(times, key=times.get) if times else cur
         if cur in times and times[pick] > (1.0 - NOISE) * times[cur]:
             pick = cur
         half = (half & ~(1 << n)) | ((1 if pick == 128 else 0) << n)
         wide = (wide & ~(1 << n)) | ((1 if pick == 512 else 0) << n)
+        wider = (wider & ~(1 << n)) | ((1 if pick == 1024 else 0) << n)
         apply(pick, n)
         results[f"n={n}"] = {"arrays": count, "ms_256": times.get(256), "ms_128": times.get(128),
-                             "ms_512": times.get(512), "threads": pick}
+                             "ms_512": times.get(512), "ms_1024": times.get(1024), "threads": pick}
         del case
         torch.cuda.empty_cache()
     set_tuning(hn, half)
     set_tuning(wn, wide)
-    log(f"{hn} -> {half:#x}, {wn} -> {wide:#x}")
-    return {hn: half, wn: wide}, {"workloads": [f"{width} fixed n=2..16"], "results": results,
-                                  "rejected": rejected, "best": {"fixed_half": half, "fixed_wide": wide}}
+    set_tuning(xn, wider)
+    log(f"{hn} -> {half:#x}, {wn} -> {wide:#x}, {xn} -> {wider:#x}")
+    return {hn: half, wn: wide, xn: wider}, {"workloads": [f"{width} fixed n=2..16"], "results": results,
+                                             "rejected": rejected,
+                                             "best": {"fixed_half": half, "fixed_wide": wide, "fixed_wider": wider}}
 
 
 def tune(quick=False, reps=5, log=print):
@@ -290,7 +295,7 @@ def tune(quick=False, reps=5, log=print):
     order = [(wd, k) for wd in ("u32", "u64") for k in PER_WIDTH] + [("all", k) for k in GLOBAL]
     for width, knob in order:
         name = knob if width == "all" else f"{width}.{knob}"
-        if knob == "fixed_half":  # with fixed_wide: one choice per n among three tile forms
+        if knob == "fixed_half":  # with fixed_wide(r): one choice per n among four tile forms
             masks, report[f"{width}.tile_threads"] = _tune_tile_threads(width, quick, reps, log)
             best.update(masks)
             continue

@@ -196,6 +196,7 @@ static const std::vector<TuneEntry>& tune_table() {
       {"fixed_apt", &Tuning::fixed_apt, 1, 4, false, true},
       {"fixed_half", &Tuning::fixed_half, 0, 0x1FFFC, false, true},
       {"fixed_wide", &Tuning::fixed_wide, 0, 0x1FFFC, false, true},
+      {"fixed_wider", &Tuning::fixed_wider, 0, 0x1FFFC, false, true},
       {"rss_finish", &Tuning::rss_finish, 0, 1, false, true},
       {"persist_occ", &Tuning::persist_occ, 0, 16, false, false},
       {"rss_rounds", &Tuning::rss_rounds, 1, 64, false, false},
@@ -235,7 +236,9 @@ static bool valid_value(const TuneEntry& e, int64_t value, const Tuning& t) {
   if (value < e.lo || value > e.hi) return false;
   if (e.pow2_k && (value & (value - 1)) != 0) return false;
   if (e.slot == &Tuning::fixed_apt && value == 3) return false;
-  if ((e.slot == &Tuning::fixed_half || e.slot == &Tuning::fixed_wide) && (value & 3) != 0) return false;  // bits 2..16
+  if ((e.slot == &Tuning::fixed_half || e.slot == &Tuning::fixed_wide || e.slot == &Tuning::fixed_wider) &&
+      (value & 3) != 0)
+    return false;  // bits 2..16
   // a G-lane group holds at most 4G keys; bound_tiny <= bound_small <= bound_mid
   if (e.slot == &Tuning::rss_bound_mid && value < t.rss_bound_small) return false;
   if (e.slot == &Tuning::rss_bound_small && (value > t.rss_bound_mid || value < t.rss_bound_tiny)) return false;

@@ -7,7 +7,7 @@
 // direct per-thread load would touch a different 16-byte piece of many cache
 // lines per instruction.  Instead a work-group stages its tile of arrays
 // through LDS (256 threads and arrays; per n, as tuned, 128 threads and
-// arrays, or 512 threads moving a tile of 256 arrays):
+// arrays, or 512 or 1024 threads moving a tile of 256 arrays):
 //
 //   HBM --(16-byte coalesced loads, consecutive lanes -> consecutive bytes)--> VGPRs
 //       --(LDS write in a conflict-avoiding layout)--> LDS
@@ -84,8 +84,9 @@ template <class K> __device__ __forceinline__ void lds_st(unsigned char* p, K v)
 }
 
 // One tile of A * TS arrays moved by TT threads (TT = TS = 256; 128 for a
-// one-array-per-thread tile of half the LDS; TT = 512 over TS = 256 arrays,
-// where every thread moves half as many chunks and the first 256 sort).
+// one-array-per-thread tile of half the LDS; TT = 512 or 1024 over TS = 256
+// arrays, where every thread moves a half or a quarter as many chunks and the
+// first 256 sort).
 template <int F, int N, class K, int A, int TT, int TS = TT>
 __device__ __forceinline__ void tile_sort(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
   using L = TileLayout<N, K, A, TS>;
@@ -236,6 +237,14 @@ fixed_wide_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
   tile_sort<F, N, K, 1, kWideTileThreads, kTileThreads>(keys, count, flip);
 }
 
+// The same with 1024 threads (a quarter of the chunks per thread).
+constexpr int kWiderTileThreads = 1024;
+template <int F, int N, class K>
+__global__ void __launch_bounds__(kWiderTileThreads)
+fixed_wider_tile_kernel(K* __restrict__ keys, int64_t count, KeyMap<K> flip) {
+  tile_sort<F, N, K, 1, kWiderTileThreads, kTileThreads>(keys, count, flip);
+}
+
 // Arrays of 8 bytes (uint32 n = 2): a 16-byte chunk holds two whole arrays,
 // so every thread loads its chunks straight from HBM (consecutive lanes,
 // consecutive chunks: fully coalesced), sorts them in registers and stores
@@ -297,7 +306,7 @@ fixed_direct_kernel(K* __restrict__ keys, int64_t count, int64_t stride, KeyMap<
 
 template <int F, int N, class K, int A, int TT = kTileThreads>
 static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_t s) {
-  constexpr int64_t TA = (int64_t)A * (TT == kWideTileThreads ? kTileThreads : TT);  // arrays per work-group
+  constexpr int64_t TA = (int64_t)A * (TT > kTileThreads ? kTileThreads : TT);  // arrays per work-group
   const int64_t blocks = (count + TA - 1) / TA;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   if constexpr (TT == kHalfTileThreads) {
@@ -306,6 +315,9 @@ static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_
   } else if constexpr (TT == kWideTileThreads) {
     static_assert(A == 1, "the 512-thread tile holds 256 arrays");
     hipLaunchKernelGGL((fixed_wide_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
+  } else if constexpr (TT == kWiderTileThreads) {
+    static_assert(A == 1, "the 1024-thread tile holds 256 arrays");
+    hipLaunchKernelGGL((fixed_wider_tile_kernel<F, N, K>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
   } else {
     hipLaunchKernelGGL((fixed_tile_kernel<F, N, K, A>), dim3((unsigned)blocks), dim3(TT), 0, s, keys, count, flip);
   }
@@ -314,7 +326,7 @@ static hipError_t launch_tile(K* keys, int64_t count, KeyMap<K> flip, hipStream_
 
 template <int F, int N, class K>
 static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<K> flip, int apt, bool half,
-                                 bool wide, hipStream_t s) {
+                                 bool wide, bool wider, hipStream_t s) {
   const int64_t blocks = (count + kTileThreads - 1) / kTileThreads;
   if (blocks > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const bool tiled = stride == N && (reinterpret_cast<uintptr_t>(keys) % 16) == 0;
@@ -342,7 +354,11 @@ static hipError_t launch_fixed_n(K* keys, int64_t count, int64_t stride, KeyMap<
     if constexpr (tile_fits<N, K, 2>()) {
       if (apt >= 2) return launch_tile<F, N, K, 2>(keys, count, flip, s);
     }
-    if (wide) return launch_tile<F, N, K, 1, kWideTileThreads>(keys, count, flip, s);
+    // the wide forms serve the networks (insertion sort spills under their register budget)
+    if constexpr (F != kFamilyInsertion) {
+      if (wider) return launch_tile<F, N, K, 1, kWiderTileThreads>(keys, count, flip, s);
+      if (wide) return launch_tile<F, N, K, 1, kWideTileThreads>(keys, count, flip, s);
+    }
     if (half) return launch_tile<F, N, K, 1, kHalfTileThreads>(keys, count, flip, s);
     return launch_tile<F, N, K, 1>(keys, count, flip, s);
   } else {
@@ -358,22 +374,23 @@ static hipError_t launch_fixed_f(K* keys, int n, int64_t count, int64_t stride, 
   const int apt = t.fixed_apt;
   const bool half = ((t.fixed_half >> n) & 1) != 0;
   const bool wide = ((t.fixed_wide >> n) & 1) != 0;
+  const bool wider = ((t.fixed_wider >> n) & 1) != 0;
   switch (n) {
-    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, half, wide, s);
-    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, half, wide, s);
-    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, half, wide, s);
-    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, half, wide, s);
-    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, half, wide, s);
-    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, half, wide, s);
-    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, half, wide, s);
-    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, half, wide, s);
-    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, half, wide, s);
-    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, half, wide, s);
-    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, half, wide, s);
-    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, half, wide, s);
-    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, half, wide, s);
-    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, half, wide, s);
-    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, half, wide, s);
+    case 2: return launch_fixed_n<F, 2>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 3: return launch_fixed_n<F, 3>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 4: return launch_fixed_n<F, 4>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 5: return launch_fixed_n<F, 5>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 6: return launch_fixed_n<F, 6>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 7: return launch_fixed_n<F, 7>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 8: return launch_fixed_n<F, 8>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 9: return launch_fixed_n<F, 9>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 10: return launch_fixed_n<F, 10>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 11: return launch_fixed_n<F, 11>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 12: return launch_fixed_n<F, 12>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 13: return launch_fixed_n<F, 13>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 14: return launch_fixed_n<F, 14>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 15: return launch_fixed_n<F, 15>(keys, count, stride, flip, apt, half, wide, wider, s);
+    case 16: return launch_fixed_n<F, 16>(keys, count, stride, flip, apt, half, wide, wider, s);
     default: return hipErrorInvalidValue;
   }
 }

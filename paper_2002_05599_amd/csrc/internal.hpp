@@ -24,7 +24,8 @@ struct Tuning {
   int rss_oversample = 3;    // oversampling a of the RSS levels with 4 buckets (1..4)
   int fixed_apt = 1;         // arrays per thread of the fixed-layout network kernels (1, 2, 4)
   int fixed_half = 0;        // bit n: arrays of n keys use the 128-thread one-array-per-thread tile
-  int fixed_wide = 0;        // bit n: ... the 512-thread tile of 256 arrays (takes precedence)
+  int fixed_wide = 0;        // bit n: ... the 512-thread tile of 256 arrays (over fixed_half)
+  int fixed_wider = 0;       // bit n: ... the 1024-thread tile of 256 arrays (over both)
   int rss_bound_tiny = 16;   // largest segment sorted by an 8-lane RSS group (16 = none, ..32)
   int rss_finish = 0;        // RSS buckets finished by 0 networks, 1 rank counting
 };

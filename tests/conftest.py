@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 # every tuning knob the library exposes (include/smallsort.h); the per-width
 # ones are snapshot per width
 PER_WIDTH_KNOBS = ("family", "rss_k_small", "rss_k_mid", "rss_k_large", "rss_bound_tiny", "rss_bound_small",
-                   "rss_bound_mid", "rss_oversample", "fixed_apt", "fixed_half", "fixed_wide",
+                   "rss_bound_mid", "rss_oversample", "fixed_apt", "fixed_half", "fixed_wide", "fixed_wider",
                    "rss_finish")
 GLOBAL_KNOBS = ("persist_occ", "rss_rounds", "interleave", "persist_split", "net_mix", "rss_level_cap",
                 "large_sort")

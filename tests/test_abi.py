@@ -160,7 +160,7 @@ def test_per_width_tuning(lib):
     a plain get of differing widths reads -2; global knobs take no prefix;
     the lane-group bounds stay ordered; the tile-form masks take bits 2..16."""
     from helpers import tuned
-    with tuned(family=1, rss_bound_small=64, rss_bound_mid=128, fixed_half=0, fixed_wide=0):
+    with tuned(family=1, rss_bound_small=64, rss_bound_mid=128, fixed_half=0, fixed_wide=0, fixed_wider=0):
         ss.set_tuning("u64.family", 0)
         assert ss.get_tuning("u32.family") == 1 and ss.get_tuning("u64.family") == 0
         assert ss.get_tuning("family") == -2
@@ -179,7 +179,7 @@ def test_per_width_tuning(lib):
             ss.set_tuning("rss_oversample", v)
         with pytest.raises(ss.SmallSortError):
             ss.set_tuning("rss_oversample", 5)
-        for knob in ("fixed_half", "fixed_wide"):
+        for knob in ("fixed_half", "fixed_wide", "fixed_wider"):
             ss.set_tuning(f"u32.{knob}", 0x1FFFC)
             ss.set_tuning(f"u64.{knob}", 1 << 16)
             assert ss.get_tuning(f"u32.{knob}") == 0x1FFFC and ss.get_tuning(f"u64.{knob}") == 1 << 16

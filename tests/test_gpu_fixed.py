@@ -164,18 +164,19 @@ def test_config1_exact():
     assert (got == want).all(), first_mismatch(got, want, 8)
 
 
-@pytest.mark.parametrize("apt,half,wide", [(1, 0, 0), (2, 0, 0), (4, 0, 0), (1, 0x1FFFC, 0), (1, 0x0AAA8, 0),
-                                           (2, 0x1FFFC, 0), (1, 0, 0x1FFFC), (1, 0x1FFFC, 0x15554),
-                                           (2, 0, 0x1FFFC)],
+@pytest.mark.parametrize("apt,half,wide,wider", [(1, 0, 0, 0), (2, 0, 0, 0), (4, 0, 0, 0), (1, 0x1FFFC, 0, 0),
+                                                 (1, 0x0AAA8, 0, 0), (2, 0x1FFFC, 0, 0), (1, 0, 0x1FFFC, 0),
+                                                 (1, 0x1FFFC, 0x15554, 0), (2, 0, 0x1FFFC, 0), (1, 0, 0, 0x1FFFC),
+                                                 (1, 0x0AAA8, 0x15554, 0x0CCCC)],
                          ids=["apt1", "apt2", "apt4", "apt1-half", "apt1-half-odd", "apt2-half", "apt1-wide",
-                              "apt1-wide-even-half-odd", "apt2-wide"])
+                              "apt1-wide-even-half-odd", "apt2-wide", "apt1-wider", "apt1-mixed"])
 @pytest.mark.parametrize("dtype", [np.uint32, np.int64, np.float32], ids=lambda d: np.dtype(d).name)
-def test_arrays_per_thread(apt, half, wide, dtype):
+def test_arrays_per_thread(apt, half, wide, wider, dtype):
     """Tiles of 1, 2 or 4 arrays per thread (reduced where the tile would not
     fit), and, where one array per thread is used, tiles staged by 128-thread
-    work-groups or by 512-thread work-groups over 256 arrays, for every n or
-    for alternate n: several tiles and a ragged tail for every n."""
-    with tuned(fixed_apt=apt, fixed_half=half, fixed_wide=wide):
+    work-groups or by 512- or 1024-thread work-groups over 256 arrays, for
+    every n or mixed across n: several tiles and a ragged tail for every n."""
+    with tuned(fixed_apt=apt, fixed_half=half, fixed_wide=wide, fixed_wider=wider):
         for n in range(2, 17):
             count = 3 * 1024 + 77
             a = (inputs.float_keys(dtype, n * count, seed=n) if np.dtype(dtype).kind == "f"
